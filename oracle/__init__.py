@@ -1,0 +1,191 @@
+"""FP64 CPU oracle for nuclear two-point correlators -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check and the CPU-baseline leg of the benchmark may
+import this package. It shares no code with the GPU library
+(``paper_2411_08962_amd``) and never imports it.
+
+Routes to C(t) for one time slice (all FP64, compensated accumulation):
+
+* ``bruteforce``: Wick's theorem quark by quark (Sec. 3.1, the expansion that
+  precedes Eq. 2.8), each nucleon summed over its own site (zero-momentum
+  nucleon sinks, Eqs. 2.4-2.6, App. D). The definition itself; small lattices.
+* ``sum_full``: blocks (Eq. 2.4 / App. D), then every source index tuple and
+  every flavor-preserving bijection with its sign (Eq. 2.6 / App. D).
+* ``sum_dp``: blocks, the source antisymmetrised first (method A, Sec. 3.3),
+  then a dynamic programme over used source positions.
+
+The sign of a bijection is its sign as a permutation of quark positions, so
+the flavor-grouping factor eta of Eq. 2.8 is part of every term; the overall
+(-1)^n / Z is dropped, as in the paper.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from . import conventions, operators  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_SO = os.path.join(_HERE, "_liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle's C core with gcc (plain -O2, OpenMP)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        L.oracle_block_raw.argtypes = [i64, P, P, P, i32, P, P, P, P]
+        L.oracle_block_eq24.argtypes = [i64, P, P, P, i32, P, P, P, P]
+        kinds = [i32, P, P, P, P, P, P]
+        pats = [i32, P, P, i32, P, P]
+        L.oracle_bruteforce.argtypes = [i32, i64, P, P] + kinds + pats + [i32, P]
+        L.oracle_count_bijections.argtypes = [i32, P, P]
+        L.oracle_count_bijections.restype = ctypes.c_long
+        L.oracle_sum_full.argtypes = [i32, P] + kinds + pats + [P]
+        L.oracle_sum_dp.argtypes = [i32, P] + kinds + pats + [P]
+        L.oracle_source_group_count.argtypes = [i32] + kinds + [i32, P, P, i32]
+        L.oracle_source_group_count.restype = ctypes.c_long
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _Packed:
+    """The operator as flat arrays for the C routines (keeps them alive)."""
+
+    def __init__(self, op):
+        K = len(op.kinds)
+        self.flav = np.array([f for k in op.kinds for f in k.flavors], dtype=np.int32)
+        self.nw = np.array([len(k.w) for k in op.kinds], dtype=np.int32)
+        self.woff = np.concatenate([[0], np.cumsum(self.nw)[:-1]]).astype(np.int32)
+        ws = [e for k in op.kinds for e in k.w]
+        self.wj = np.array([[e[0], e[1], e[2]] for e in ws], dtype=np.int32).reshape(-1)
+        self.wre = np.array([e[3] for e in ws], dtype=np.float64)
+        self.wim = np.array([e[4] for e in ws], dtype=np.float64)
+        self.K = K
+        self.snk_k = np.array([k for p in op.snk for k in p[0]], dtype=np.int32)
+        self.snk_c = np.array([c for p in op.snk for c in p[1]], dtype=np.float64)
+        self.src_k = np.array([k for p in op.src for k in p[0]], dtype=np.int32)
+        self.src_c = np.array([c for p in op.src for c in p[1]], dtype=np.float64)
+        self.n_snk, self.n_src = len(op.snk), len(op.src)
+
+    def kinds_args(self):
+        return [self.K, _p(self.flav), _p(self.nw), _p(self.woff), _p(self.wj), _p(self.wre), _p(self.wim)]
+
+    def pat_args(self):
+        return [self.n_snk, _p(self.snk_k), _p(self.snk_c), self.n_src, _p(self.src_k), _p(self.src_c)]
+
+
+def _site_major(S):
+    S = np.ascontiguousarray(S, dtype=np.complex128)
+    return S.reshape(-1, 12, 12)
+
+
+def block_raw(kind, Su_t, Sd_t):
+    """B[i1, i2, i3] of one kind at one time slice (the block formula, raw)."""
+    Su, Sd = _site_major(Su_t), _site_major(Sd_t)
+    flav = np.array(kind.flavors, dtype=np.int32)
+    wj = np.array([[e[0], e[1], e[2]] for e in kind.w], dtype=np.int32).reshape(-1)
+    wre = np.array([e[3] for e in kind.w], dtype=np.float64)
+    wim = np.array([e[4] for e in kind.w], dtype=np.float64)
+    B = np.zeros(1728, dtype=np.complex128)
+    lib().oracle_block_raw(Su.shape[0], _p(Su), _p(Sd), _p(flav), len(kind.w), _p(wj), _p(wre), _p(wim), _p(B))
+    return B.reshape(12, 12, 12)
+
+
+def block_eq24(kind, Su_t, Sd_t):
+    """The block of Eq. 2.4: antisymmetrised in its two same-flavor source slots (1 and 3)."""
+    assert kind.flavors[0] == kind.flavors[2]
+    Su, Sd = _site_major(Su_t), _site_major(Sd_t)
+    flav = np.array(kind.flavors, dtype=np.int32)
+    wj = np.array([[e[0], e[1], e[2]] for e in kind.w], dtype=np.int32).reshape(-1)
+    wre = np.array([e[3] for e in kind.w], dtype=np.float64)
+    wim = np.array([e[4] for e in kind.w], dtype=np.float64)
+    B = np.zeros(1728, dtype=np.complex128)
+    lib().oracle_block_eq24(Su.shape[0], _p(Su), _p(Sd), _p(flav), len(kind.w), _p(wj), _p(wre), _p(wim), _p(B))
+    return B.reshape(12, 12, 12)
+
+
+def blocks_raw(op, Su_t, Sd_t):
+    return np.stack([block_raw(k, Su_t, Sd_t) for k in op.kinds])
+
+
+def bruteforce(op, Su_t, Sd_t, by_flavor=False, with_magnitude=False):
+    """C at one time slice from the quark-level definition (unscaled).
+
+    ``by_flavor`` sums the bijections flavor by flavor (the determinant form of
+    Eqs. 2.8-2.9) instead of over all positions at once. ``with_magnitude``
+    also returns the sum of the absolute values of the summed products, a
+    scale for rounding-level comparisons.
+    """
+    pk = _Packed(op)
+    Su, Sd = _site_major(Su_t), _site_major(Sd_t)
+    out = np.zeros(3)
+    lib().oracle_bruteforce(op.A, Su.shape[0], _p(Su), _p(Sd), *pk.kinds_args(), *pk.pat_args(),
+                            1 if by_flavor else 0, _p(out))
+    c = complex(out[0], out[1])
+    return (c, float(out[2])) if with_magnitude else c
+
+
+def sum_full(op, B):
+    pk = _Packed(op)
+    B = np.ascontiguousarray(B, dtype=np.complex128)
+    out = np.zeros(2)
+    lib().oracle_sum_full(op.A, _p(B), *pk.kinds_args(), *pk.pat_args(), _p(out))
+    return complex(out[0], out[1])
+
+
+def sum_dp(op, B):
+    pk = _Packed(op)
+    B = np.ascontiguousarray(B, dtype=np.complex128)
+    out = np.zeros(2)
+    lib().oracle_sum_dp(op.A, _p(B), *pk.kinds_args(), *pk.pat_args(), _p(out))
+    return complex(out[0], out[1])
+
+
+def count_bijections(f, g):
+    """Number of flavor-preserving bijections between two flavor listings."""
+    f = np.asarray(f, dtype=np.int32)
+    g = np.asarray(g, dtype=np.int32)
+    return int(lib().oracle_count_bijections(len(f), _p(f), _p(g)))
+
+
+def source_group_count(op):
+    pk = _Packed(op)
+    nu = sum(1 for f in operators.flavor_listing(op, op.snk[0][0]) if f == 0)
+    return int(lib().oracle_source_group_count(op.A, *pk.kinds_args(), pk.n_src, _p(pk.src_k), _p(pk.src_c), nu))
+
+
+def correlator(op, Su, Sd, route="dp", t_slices=None):
+    """Scaled C(t) for the time slices of ``Su, Sd`` ([T, Z, Y, X, 12, 12])."""
+    T = Su.shape[0]
+    ts = range(T) if t_slices is None else t_slices
+    out = np.zeros(len(ts), dtype=np.complex128)
+    for n, t in enumerate(ts):
+        if route == "bruteforce":
+            c = bruteforce(op, Su[t], Sd[t])
+        else:
+            B = blocks_raw(op, Su[t], Sd[t])
+            c = sum_full(op, B) if route == "full" else sum_dp(op, B)
+        out[n] = op.scale * c
+    return out
