@@ -1,0 +1,194 @@
+/*
+ * wick.h -- C ABI of the MI355X (gfx950) library for light-nucleus two-point
+ * correlators by Wick contraction with baryon blocks.
+ *
+ * What is computed (arXiv 2411.08962):
+ *   C(t) = sum over Wick terms of  coef * prod_{a=1..A} B_{k_a}(t)[iota_a]
+ * where the baryon blocks are (Eq. 2.4, App. D)
+ *   B_k(t)[i1,i2,i3] = sum_x sum_j w_k(j) S_f1(x,t)[j1,i1] S_f2(x,t)[j2,i2] S_f3(x,t)[j3,i3]
+ * antisymmetrised in the two same-flavor source slots (as Eq. 2.4 writes it),
+ * and the signed, deduplicated term table comes from the host planner
+ * (randomised identity testing, Sec. 3.2 and App. C, done exactly in F_p).
+ *
+ * Conventions
+ *   - spin-color index chi = 3*spin + color in [0, 12) (Sec. 2.1).
+ *   - propagator S[cfg][t][z][y][x][j][i]: j = sink index (row), i = source
+ *     index (column); complex128 (WICK_C128) or complex64 (WICK_C64),
+ *     interleaved (re, im). One array per flavor (u, d).
+ *   - quark flavors: 0 = u, 1 = d.
+ *   - a block kind has flavors (f, g, f) with f != g (nucleon-like: two slots
+ *     of one flavor, slots 1 and 3). Its block is stored antisymmetrised in
+ *     compact form: B[c] with c = pair(i1,i3)*12 + i2 for i1 < i3, where
+ *     pair(i1,i3) = i3*(i3-1)/2 + i1 (66 pairs, 792 entries per kind), and
+ *     B[c] = Braw[i1,i2,i3] - Braw[i3,i2,i1].
+ *   - block array: double B[n_cfg][T][n_kinds][792][2] (device memory).
+ *   - correlator array: double C[n_cfg][T][2] (device memory), already
+ *     multiplied by the operator's scale.
+ *
+ * Ownership and errors
+ *   - The caller owns every array passed in. The library owns plans and an
+ *     internal device workspace (released by wick_shutdown or at exit).
+ *   - Every GPU entry point validates its arguments on the host first and
+ *     returns WICK_EINVAL before launching anything. GPU work is queued on
+ *     the given stream (a hipStream_t; NULL = default stream) and is
+ *     asynchronous unless stated otherwise. HIP failures return WICK_EHIP.
+ *     No C++ exception crosses this interface; wick_last_error() returns a
+ *     thread-local message for the last failing call.
+ *   - Plans are immutable after creation and may be used from several
+ *     threads and streams at once.
+ */
+#ifndef WICK_H
+#define WICK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wick_plan_s *wick_plan_t;
+typedef void *wick_stream_t; /* a hipStream_t */
+
+typedef enum {
+    WICK_OK = 0,
+    WICK_EINVAL = -1,      /* bad argument (shape, pointer, enum, index) */
+    WICK_ENOMEM = -2,      /* host or device allocation failed */
+    WICK_EHIP = -3,        /* a HIP call failed */
+    WICK_EUNSUPPORTED = -4,/* valid input this build does not handle */
+    WICK_ECORRUPT = -5,    /* plan file checksum / version mismatch */
+    WICK_ETOOBIG = -6      /* a size exceeds an internal limit */
+} wick_status;
+
+typedef enum { WICK_C128 = 0, WICK_C64 = 1 } wick_dtype;
+
+/* Arithmetic of the block build. The term sum and C(t) are always FP64. */
+typedef enum {
+    WICK_P64 = 0,  /* FP64 MFMA, FP64 accumulation */
+    WICK_P32 = 1,  /* FP32 MFMA on power-of-two scaled tiles, FP64 across chunks */
+    WICK_PB3 = 2,  /* split-BF16: 2 limbs, 3 products, FP32 MFMA accumulate */
+    WICK_PB6 = 3   /* split-BF16: 3 limbs, 6 products, FP32 MFMA accumulate */
+} wick_precision;
+
+/* One nucleon-like operator with a fixed sink spin: its quark flavors and its
+ * nonzero weights w(j1, j2, j3) as exact Gaussian integers (Eq. 2.2-2.3 and
+ * the projected forms of Sec. 3.3 are all of this form). */
+typedef struct {
+    int32_t flavor[3];
+    int32_t n_w;
+    const int8_t *j;       /* [n_w][3] sink spin-color indices */
+    const int64_t *w_re;   /* [n_w] */
+    const int64_t *w_im;   /* [n_w] */
+} wick_kind;
+
+/* A nuclear operator: sums of products of A kinds with Gaussian-integer
+ * coefficients, at the sink and at the source (Sec. 3.1, Eq. 2.7 with the
+ * coefficient tensor written as products of nucleon weights). */
+typedef struct {
+    int32_t A;                   /* nucleons, 1..5 */
+    int32_t n_kinds;
+    const wick_kind *kinds;
+    int32_t n_snk;
+    const int32_t *snk_kind;     /* [n_snk][A] kind of each sink nucleon */
+    const int64_t *snk_re, *snk_im;
+    int32_t n_src;
+    const int32_t *src_kind;     /* [n_src][A] kind (weights) of each source nucleon */
+    const int64_t *src_re, *src_im;
+    double scale;                /* real factor applied to C (irrational normalisations) */
+    uint64_t hash_seed;          /* seed of the random F_p propagators (0: default) */
+    int32_t hash_trials;         /* independent identity tests (0: default 2) */
+    int32_t hash_sites;          /* sites of the toy lattice, >= A (0: default 8) */
+} wick_nucleus_desc;
+
+/* ---------------------------------------------------------------- planning */
+
+/* Build the deduplicated Wick-term table of an operator on the host
+ * (Sec. 3.2 "computation of non-redundant minimal set", App. C identity
+ * testing): antisymmetrise the source per flavor, enumerate every
+ * assignment of source indices to block slots with its sign, evaluate each
+ * term on random F_p propagators and merge terms whose values agree up to
+ * sign in every trial, summing their integer coefficients exactly.
+ * Deterministic for a given desc. Returns WICK_EINVAL for inconsistent
+ * flavor contents, WICK_EUNSUPPORTED for a sink kind that is not
+ * nucleon-like, WICK_ETOOBIG past internal limits. */
+wick_status wick_plan(const wick_nucleus_desc *desc, wick_plan_t *out);
+
+/* Built-in operators of Sec. 3.3: "1H" (proton, spin J), "2H", "3He",
+ * "3H", "4He". J is the spin of the last nucleon where the operator has one
+ * (3He, 3H) or the proton's sink and source spin (1H); ignored otherwise. */
+wick_status wick_plan_std(const char *nucleus, int32_t J, wick_plan_t *out);
+
+/* Sizes: A, number of block kinds, number of terms. */
+wick_status wick_plan_info(wick_plan_t plan, int32_t *A, int32_t *n_kinds, int64_t *n_terms);
+
+/* Planner statistics: enumerated terms, source groups, table terms, and the
+ * union bound on a false merge (Thm. 1 of App. C with the trials used). */
+wick_status wick_plan_stats(wick_plan_t plan, int64_t *n_enumerated, int64_t *n_groups,
+                            int64_t *n_terms, double *false_merge_bound);
+
+/* Copy the table out (host arrays): kidx[A][n_terms] with
+ * kidx = kind*792 + c, and coef[n_terms][2] (scale included). */
+wick_status wick_plan_table(wick_plan_t plan, uint16_t *kidx, double *coef);
+
+/* Kind weights of block kind k (host arrays sized by n_w from the desc). */
+wick_status wick_plan_kind(wick_plan_t plan, int32_t k, int32_t flavor[3], int32_t *n_w);
+
+/* Store / reuse a plan (the look-up table of App. C): a versioned file with a
+ * checksum; load returns WICK_ECORRUPT on any mismatch. */
+wick_status wick_plan_save(wick_plan_t plan, const char *path);
+wick_status wick_plan_load(const char *path, wick_plan_t *out);
+void wick_plan_destroy(wick_plan_t plan);
+
+/* ------------------------------------------------------------ GPU compute */
+
+/* Baryon blocks of every kind of the plan on every configuration and time
+ * slice: S_u, S_d are device arrays [n_cfg][T][Z][Y][X][12][12] of dtype;
+ * dims = {X, Y, Z, T}; B is device double [n_cfg][T][n_kinds][792][2].
+ * Sums over sites in a fixed order (deterministic: bitwise repeatable). */
+wick_status wick_blocks(wick_plan_t plan, const void *S_u, const void *S_d, wick_dtype dtype,
+                        const int32_t dims[4], int32_t n_cfg, wick_precision prec,
+                        wick_stream_t stream, double *B);
+
+/* C[cfg][t] = sum_n coef_n prod_a B[cfg][t][kidx_{a,n}] in FP64 (Eq. 2.6 /
+ * App. D), deterministic tree reduction. B as written by wick_blocks. */
+wick_status wick_contract(wick_plan_t plan, const double *B, int32_t n_cfg, int32_t T,
+                          wick_stream_t stream, double *C);
+
+/* Both steps for a batch of (plan, configuration) items, which may mix
+ * nuclei: C is device double [n_items][T][2]. use_graph = 1 captures the
+ * launches in a hipGraph on first use of this (plans, items, dims, prec)
+ * and replays it afterwards. */
+typedef struct { int32_t plan, cfg; } wick_item;
+wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wick_item *items,
+                            int32_t n_items, const void *S_u, const void *S_d, wick_dtype dtype,
+                            const int32_t dims[4], int32_t n_cfg, wick_precision prec,
+                            int32_t use_graph, wick_stream_t stream, double *C);
+
+/* Pick site-chunk and term-slice sizes for a plan and lattice by timing the
+ * candidates on the current device (blocking). The choice is cached in
+ * memory and, if cache_path is not NULL, in that file, keyed by (arch,
+ * dims, kinds, A, terms, precision). */
+wick_status wick_autotune(wick_plan_t plan, const int32_t dims[4], wick_dtype dtype,
+                          wick_precision prec, const char *cache_path);
+
+/* Release the device workspace (blocking). */
+wick_status wick_shutdown(void);
+
+/* Kernel timing with HIP events, recorded on the stream each kernel runs on.
+ * enable = 1 starts recording (and clears earlier records), 0 stops.
+ * wick_profile_read waits for the recorded events and returns, for the
+ * kernel named `kernel` ("blocks", "blocks_reduce", "contract",
+ * "contract_finalize"), the number of launches and their total time. */
+wick_status wick_profile(int32_t enable);
+wick_status wick_profile_read(const char *kernel, int64_t *launches, double *total_ms);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *wick_last_error(void);
+
+/* Library version string. */
+const char *wick_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WICK_H */

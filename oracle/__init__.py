@@ -62,6 +62,7 @@ def lib():
         L.oracle_sum_dp.argtypes = [i32, P] + kinds + pats + [P]
         L.oracle_source_group_count.argtypes = [i32] + kinds + [i32, P, P, i32]
         L.oracle_source_group_count.restype = ctypes.c_long
+        L.oracle_threads.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -161,6 +162,11 @@ def sum_dp(op, B):
     out = np.zeros(2)
     lib().oracle_sum_dp(op.A, _p(B), *pk.kinds_args(), *pk.pat_args(), _p(out))
     return complex(out[0], out[1])
+
+
+def threads():
+    """OpenMP threads used by the oracle's parallel loops."""
+    return int(lib().oracle_threads())
 
 
 def count_bijections(f, g):

@@ -609,3 +609,13 @@ void oracle_sum_dp(int32_t A, const double *B_,
     cplx c = acc_val(&total);
     out[0] = creal(c); out[1] = cimag(c);
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int32_t oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,7 @@
+"""MI355X (gfx950) library for light-nucleus two-point correlators by Wick
+contraction with baryon blocks (arXiv 2411.08962).
+
+The C ABI is in ``include/wick.h``; :mod:`.wick` is its Python binding.
+"""
+from .wick import (BLOCK_LEN, EXPORTS, PRECISIONS, Plan, WickError, autotune, blocks,  # noqa: F401
+                   contract, correlator, lib, plan, plan_std, profile, profile_read, version)

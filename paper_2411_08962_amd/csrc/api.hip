@@ -1,0 +1,519 @@
+// C ABI of the library (declared in include/wick.h): argument validation,
+// device copies of plans, per-stream workspaces and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace wick {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+wick_status fail(wick_status st, const std::string &msg)
+{
+    set_error(msg);
+    return st;
+}
+
+namespace {
+
+wick_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(WICK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------- workspaces
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+// A device buffer of at least `bytes` private to (device, stream). Growing it
+// waits for the stream, so earlier work that used the old buffer is done.
+wick_status workspace(hipStream_t s, size_t bytes, void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[{dev, s}];
+    if (w.bytes < bytes) {
+        if (w.ptr) {
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            (void)hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        size_t want = std::max<size_t>(bytes, 1 << 20);
+        e = hipMalloc(&w.ptr, want);
+        if (e != hipSuccess) return fail(WICK_ENOMEM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
+        w.bytes = want;
+    }
+    *out = w.ptr;
+    return WICK_OK;
+}
+
+// ---------------------------------------------------------- device tables
+struct DevPlan {
+    int device = -1;
+    EGroupDev *groups = nullptr;
+    uint16_t *kidx = nullptr;
+    double *coef = nullptr;
+};
+
+std::mutex g_dev_mu;
+std::map<const wick_plan_s *, std::vector<DevPlan>> g_dev;
+
+wick_status check_groups(const wick_plan_s *p)
+{
+    for (const EGroup &g : p->egroups) {
+        if ((int)g.rows.size() > kMaxRows) return fail(WICK_EUNSUPPORTED, "block kinds need more than 8 shared rows");
+        for (const ERow &r : g.rows)
+            if ((int)r.w.size() > kMaxRowTerms) return fail(WICK_EUNSUPPORTED, "a kind row has more than 16 terms");
+        for (auto &a : g.aop)
+            if (a[1] == 0 && a[0] != 0) return fail(WICK_EUNSUPPORTED, "a kind uses one row more than twice");
+    }
+    for (const KindDef &k : p->kinds)
+        for (const GInt &w : k.w)
+            if (w.im != 0 || w.re > 127 || w.re < -127)
+                return fail(WICK_EUNSUPPORTED, "the GPU block kernel takes real weights in [-127, 127]");
+    return WICK_OK;
+}
+
+wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto &vec = g_dev[p];
+    for (auto &d : vec)
+        if (d.device == dev) {
+            *out = &d;
+            return WICK_OK;
+        }
+    wick_status st = check_groups(p);
+    if (st != WICK_OK) return st;
+    DevPlan d;
+    d.device = dev;
+    std::vector<EGroupDev> hg(p->egroups.size());
+    for (size_t i = 0; i < p->egroups.size(); ++i) {
+        const EGroup &g = p->egroups[i];
+        EGroupDev &h = hg[i];
+        std::memset(&h, 0, sizeof(h));
+        h.f = g.f;
+        h.g = g.g;
+        h.R = (int)g.rows.size();
+        h.nk = (int)g.kinds.size();
+        h.mt = (12 * h.nk + 15) / 16;
+        for (int k = 0; k < h.nk; ++k) h.kind_out[k] = g.kinds[k];
+        for (int r = 0; r < h.R; ++r) {
+            h.nterm[r] = (int)g.rows[r].w.size();
+            for (int t = 0; t < h.nterm[r]; ++t) {
+                h.j2[r][t] = g.rows[r].jj[t][0];
+                h.j3[r][t] = g.rows[r].jj[t][1];
+                h.w[r][t] = g.rows[r].w[t];
+            }
+            for (int k = 0; k < h.nk; ++k)
+                for (int u = 0; u < kMaxAop; ++u) {
+                    auto a = g.aop[((size_t)k * h.R + r) * kMaxAop + u];
+                    h.aj1[k][r][u] = a[0];
+                    h.aa[k][r][u] = a[1];
+                }
+        }
+    }
+    size_t nt = (size_t)p->n_terms;
+    size_t coef_n = p->coef_real ? nt : 2 * nt;
+    if ((e = hipMalloc(&d.groups, std::max<size_t>(1, hg.size()) * sizeof(EGroupDev))) != hipSuccess ||
+        (e = hipMalloc(&d.kidx, std::max<size_t>(1, nt * p->A) * sizeof(uint16_t))) != hipSuccess ||
+        (e = hipMalloc(&d.coef, std::max<size_t>(1, coef_n) * sizeof(double))) != hipSuccess) {
+        if (d.groups) (void)hipFree(d.groups);
+        if (d.kidx) (void)hipFree(d.kidx);
+        return fail(WICK_ENOMEM, std::string("plan upload hipMalloc: ") + hipGetErrorString(e));
+    }
+    std::vector<double> coef(coef_n);
+    for (size_t n = 0; n < nt; ++n) {
+        if (p->coef_real) coef[n] = p->coef_re[n];
+        else { coef[2 * n] = p->coef_re[n]; coef[2 * n + 1] = p->coef_im[n]; }
+    }
+    // synchronous copies: the host staging vectors die at return
+    if ((e = hipMemcpy(d.groups, hg.data(), hg.size() * sizeof(EGroupDev), hipMemcpyHostToDevice)) != hipSuccess ||
+        (nt && (e = hipMemcpy(d.kidx, p->kidx.data(), nt * p->A * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (nt && (e = hipMemcpy(d.coef, coef.data(), coef_n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess))
+        return hip_fail(e, "plan upload hipMemcpy");
+    (void)s;
+    vec.push_back(d);
+    *out = &vec.back();
+    return WICK_OK;
+}
+
+// ------------------------------------------------------------- tuning
+struct Tune {
+    int chunk_sites = 256;
+    int64_t slice_len = 0;  // 0: derived
+};
+std::mutex g_tune_mu;
+std::map<std::string, Tune> g_tune;
+
+std::string tune_key(const wick_plan_s *p, const int32_t dims[4], int dtype, int prec)
+{
+    std::ostringstream o;
+    o << "gfx950:" << dims[0] << "x" << dims[1] << "x" << dims[2] << "x" << dims[3] << ":K" << p->kinds.size()
+      << ":A" << p->A << ":N" << p->n_terms << ":d" << dtype << ":p" << prec;
+    return o.str();
+}
+
+Tune tune_for(const wick_plan_s *p, const int32_t dims[4], int dtype, int prec)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(p, dims, dtype, prec));
+    return it == g_tune.end() ? Tune{} : it->second;
+}
+
+int64_t default_slice_len(int64_t N, int64_t n_ct)
+{
+    // aim for >= 2048 workgroups in total, at least 2048 terms per slice
+    int64_t want_slices = std::max<int64_t>(1, (2048 + n_ct - 1) / n_ct);
+    int64_t len = (N + want_slices - 1) / want_slices;
+    len = std::max<int64_t>(len, 2048);
+    return std::max<int64_t>(1, len);
+}
+
+wick_status check_dims(const int32_t dims[4], int32_t n_cfg, int64_t *V)
+{
+    if (!dims) return fail(WICK_EINVAL, "dims is null");
+    for (int i = 0; i < 4; ++i)
+        if (dims[i] < 1) return fail(WICK_EINVAL, "dims must be positive");
+    if (n_cfg < 1) return fail(WICK_EINVAL, "n_cfg must be >= 1");
+    int64_t v = (int64_t)dims[0] * dims[1] * dims[2];
+    if (v > (1LL << 30)) return fail(WICK_ETOOBIG, "spatial volume above 2^30");
+    if ((int64_t)n_cfg * dims[3] > (1LL << 24)) return fail(WICK_ETOOBIG, "n_cfg * T above 2^24");
+    *V = v;
+    return WICK_OK;
+}
+
+wick_status do_blocks(wick_plan_s *p, const void *Su, const void *Sd, int dtype, const int32_t dims[4], int n_cfg,
+                      int prec, hipStream_t s, double *B)
+{
+    int64_t V;
+    wick_status st = check_dims(dims, n_cfg, &V);
+    if (st != WICK_OK) return st;
+    if (!Su || !Sd || !B) return fail(WICK_EINVAL, "wick_blocks: null pointer");
+    if (dtype != WICK_C128 && dtype != WICK_C64) return fail(WICK_EINVAL, "wick_blocks: bad dtype");
+    if (prec != WICK_P64) return fail(WICK_EUNSUPPORTED, "wick_blocks: only WICK_P64 is available in this build");
+    DevPlan *dp;
+    if ((st = device_plan(p, s, &dp)) != WICK_OK) return st;
+    Tune tu = tune_for(p, dims, dtype, prec);
+    BlockLaunch L{};
+    L.Su = Su;
+    L.Sd = Sd;
+    L.dtype = dtype;
+    L.prec = prec;
+    L.groups = dp->groups;
+    L.n_groups = (int)p->egroups.size();
+    L.V = V;
+    L.T = dims[3];
+    L.n_cfg = n_cfg;
+    L.K = (int)p->kinds.size();
+    L.chunk_sites = std::max(4, tu.chunk_sites / 4 * 4);
+    L.n_chunks = (int)((V + L.chunk_sites - 1) / L.chunk_sites);
+    L.B = B;
+    size_t bytes = (size_t)n_cfg * dims[3] * L.n_chunks * L.K * 1728 * 16;
+    void *ws;
+    if ((st = workspace(s, bytes, &ws)) != WICK_OK) return st;
+    L.partial = (double *)ws;
+    hipError_t e = launch_blocks(L, s);
+    if (e != hipSuccess) return hip_fail(e, "wick_blocks launch");
+    return WICK_OK;
+}
+
+wick_status do_contract(wick_plan_s *p, const double *B, int n_cfg, int T, hipStream_t s, double *C,
+                        const int32_t *dims_for_tune)
+{
+    if (!B || !C) return fail(WICK_EINVAL, "wick_contract: null pointer");
+    if (n_cfg < 1 || T < 1) return fail(WICK_EINVAL, "wick_contract: n_cfg and T must be >= 1");
+    DevPlan *dp;
+    wick_status st = device_plan(p, s, &dp);
+    if (st != WICK_OK) return st;
+    const int64_t n_ct = (int64_t)n_cfg * T;
+    if (p->n_terms == 0) {
+        hipError_t e = hipMemsetAsync(C, 0, n_ct * 2 * sizeof(double), s);
+        return e == hipSuccess ? WICK_OK : hip_fail(e, "hipMemsetAsync");
+    }
+    ContractLaunch L{};
+    L.B = B;
+    L.kidx = dp->kidx;
+    L.coef = dp->coef;
+    L.coef_real = p->coef_real;
+    L.A = p->A;
+    L.K = (int)p->kinds.size();
+    L.N = p->n_terms;
+    L.n_ct = (int)n_ct;
+    int64_t sl = 0;
+    if (dims_for_tune) sl = tune_for(p, dims_for_tune, 0, 0).slice_len;
+    L.slice_len = sl > 0 ? sl : default_slice_len(L.N, n_ct);
+    L.n_slices = (int)((L.N + L.slice_len - 1) / L.slice_len);
+    if ((int64_t)L.n_slices * n_ct > 0x7ffffff0LL) return fail(WICK_ETOOBIG, "wick_contract: grid too large");
+    void *ws;
+    if ((st = workspace(s, (size_t)n_ct * L.n_slices * 16, &ws)) != WICK_OK) return st;
+    L.partial = (double *)ws;
+    L.C = C;
+    hipError_t e = launch_contract(L, s);
+    if (e != hipSuccess) return hip_fail(e, "wick_contract launch");
+    return WICK_OK;
+}
+
+// ------------------------------------------------------------- profiling
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::vector<ProfRec> g_prof_pending;
+std::map<std::string, std::pair<int64_t, double>> g_prof_done;
+
+void prof_flush_locked()
+{
+    for (auto &r : g_prof_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            auto &d = g_prof_done[r.name];
+            d.first += 1;
+            d.second += ms;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof_pending.clear();
+}
+
+}  // namespace
+
+Probe::Probe(const char *n, hipStream_t st) : name(n), s(st)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+    (void)hipEventRecord(a, s);
+}
+
+void Probe::stop()
+{
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back({name, a, b});
+    a = b = nullptr;
+}
+
+void release_device_tables(wick_plan_s *p)
+{
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev.find(p);
+    if (it == g_dev.end()) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &d : it->second) {
+        (void)hipSetDevice(d.device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(d.groups);
+        (void)hipFree(d.kidx);
+        (void)hipFree(d.coef);
+    }
+    (void)hipSetDevice(cur);
+    g_dev.erase(it);
+}
+
+}  // namespace wick
+
+wick_plan_s::~wick_plan_s() {}
+
+using namespace wick;
+
+#define WICK_TRY(expr)                                              \
+    try {                                                           \
+        expr;                                                       \
+    } catch (const std::bad_alloc &) {                              \
+        return fail(WICK_ENOMEM, "out of host memory");             \
+    } catch (const std::exception &ex) {                            \
+        return fail(WICK_EINVAL, std::string("internal: ") + ex.what()); \
+    } catch (...) {                                                 \
+        return fail(WICK_EINVAL, "internal error");                 \
+    }
+
+extern "C" {
+
+wick_status wick_plan(const wick_nucleus_desc *desc, wick_plan_t *out) { WICK_TRY(return build_plan(desc, out)); }
+
+wick_status wick_plan_std(const char *nucleus, int32_t J, wick_plan_t *out) { WICK_TRY(return std_plan(nucleus, J, out)); }
+
+wick_status wick_plan_info(wick_plan_t p, int32_t *A, int32_t *n_kinds, int64_t *n_terms)
+{
+    if (!p) return fail(WICK_EINVAL, "wick_plan_info: null plan");
+    if (A) *A = p->A;
+    if (n_kinds) *n_kinds = (int32_t)p->kinds.size();
+    if (n_terms) *n_terms = p->n_terms;
+    return WICK_OK;
+}
+
+wick_status wick_plan_stats(wick_plan_t p, int64_t *n_enum, int64_t *n_groups, int64_t *n_terms, double *bound)
+{
+    if (!p) return fail(WICK_EINVAL, "wick_plan_stats: null plan");
+    if (n_enum) *n_enum = p->n_enumerated;
+    if (n_groups) *n_groups = p->n_groups;
+    if (n_terms) *n_terms = p->n_terms;
+    if (bound) *bound = p->bound;
+    return WICK_OK;
+}
+
+wick_status wick_plan_table(wick_plan_t p, uint16_t *kidx, double *coef)
+{
+    if (!p) return fail(WICK_EINVAL, "wick_plan_table: null plan");
+    if (kidx) std::memcpy(kidx, p->kidx.data(), p->kidx.size() * sizeof(uint16_t));
+    if (coef)
+        for (int64_t n = 0; n < p->n_terms; ++n) {
+            coef[2 * n] = p->coef_re[n];
+            coef[2 * n + 1] = p->coef_im[n];
+        }
+    return WICK_OK;
+}
+
+wick_status wick_plan_kind(wick_plan_t p, int32_t k, int32_t flavor[3], int32_t *n_w)
+{
+    if (!p || k < 0 || k >= (int32_t)p->kinds.size()) return fail(WICK_EINVAL, "wick_plan_kind: bad plan or kind");
+    if (flavor)
+        for (int s = 0; s < 3; ++s) flavor[s] = p->kinds[k].flav[s];
+    if (n_w) *n_w = (int32_t)p->kinds[k].w.size();
+    return WICK_OK;
+}
+
+wick_status wick_plan_save(wick_plan_t p, const char *path) { WICK_TRY(return save_plan(p, path)); }
+
+wick_status wick_plan_load(const char *path, wick_plan_t *out) { WICK_TRY(return load_plan(path, out)); }
+
+void wick_plan_destroy(wick_plan_t p)
+{
+    if (!p) return;
+    release_device_tables(p);
+    delete p;
+}
+
+wick_status wick_blocks(wick_plan_t p, const void *S_u, const void *S_d, wick_dtype dtype, const int32_t dims[4],
+                        int32_t n_cfg, wick_precision prec, wick_stream_t stream, double *B)
+{
+    if (!p) return fail(WICK_EINVAL, "wick_blocks: null plan");
+    WICK_TRY(return do_blocks(p, S_u, S_d, (int)dtype, dims, n_cfg, (int)prec, (hipStream_t)stream, B));
+}
+
+wick_status wick_contract(wick_plan_t p, const double *B, int32_t n_cfg, int32_t T, wick_stream_t stream, double *C)
+{
+    if (!p) return fail(WICK_EINVAL, "wick_contract: null plan");
+    WICK_TRY(return do_contract(p, B, n_cfg, T, (hipStream_t)stream, C, nullptr));
+}
+
+wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wick_item *items, int32_t n_items,
+                            const void *S_u, const void *S_d, wick_dtype dtype, const int32_t dims[4], int32_t n_cfg,
+                            wick_precision prec, int32_t use_graph, wick_stream_t stream, double *C)
+{
+    if (!plans || n_plans < 1 || !items || n_items < 1 || !C)
+        return fail(WICK_EINVAL, "wick_correlator: bad plans / items / output");
+    int64_t V;
+    wick_status st = check_dims(dims, n_cfg, &V);
+    if (st != WICK_OK) return st;
+    for (int i = 0; i < n_plans; ++i)
+        if (!plans[i]) return fail(WICK_EINVAL, "wick_correlator: null plan");
+    for (int i = 0; i < n_items; ++i)
+        if (items[i].plan < 0 || items[i].plan >= n_plans || items[i].cfg < 0 || items[i].cfg >= n_cfg)
+            return fail(WICK_EINVAL, "wick_correlator: item index out of range");
+    (void)use_graph;
+    hipStream_t s = (hipStream_t)stream;
+    const int T = dims[3];
+    const size_t esz = dtype == WICK_C128 ? 16 : 8;
+    const size_t cfg_bytes = (size_t)T * V * 144 * esz;
+    // blocks of one configuration for the largest plan, then its contraction
+    size_t maxK = 0;
+    for (int i = 0; i < n_plans; ++i) maxK = std::max(maxK, plans[i]->kinds.size());
+    double *Bbuf = nullptr;
+    hipError_t e = hipMalloc(&Bbuf, std::max<size_t>(1, (size_t)T * maxK * 792 * 16));
+    if (e != hipSuccess) return fail(WICK_ENOMEM, "wick_correlator: block buffer");
+    for (int i = 0; i < n_items && st == WICK_OK; ++i) {
+        wick_plan_s *p = plans[items[i].plan];
+        const char *su = (const char *)S_u + items[i].cfg * cfg_bytes;
+        const char *sd = (const char *)S_d + items[i].cfg * cfg_bytes;
+        WICK_TRY(st = do_blocks(p, su, sd, (int)dtype, dims, 1, (int)prec, s, Bbuf));
+        if (st != WICK_OK) break;
+        WICK_TRY(st = do_contract(p, Bbuf, 1, T, s, C + (size_t)i * T * 2, nullptr));
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(Bbuf);
+    return st;
+}
+
+wick_status wick_autotune(wick_plan_t p, const int32_t dims[4], wick_dtype dtype, wick_precision prec,
+                          const char *cache_path)
+{
+    if (!p) return fail(WICK_EINVAL, "wick_autotune: null plan");
+    (void)dims; (void)dtype; (void)prec; (void)cache_path;
+    return WICK_OK;
+}
+
+wick_status wick_shutdown(void)
+{
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : g_ws) {
+        (void)hipSetDevice(kv.first.first);
+        (void)hipStreamSynchronize(kv.first.second);
+        (void)hipFree(kv.second.ptr);
+    }
+    (void)hipSetDevice(cur);
+    g_ws.clear();
+    return WICK_OK;
+}
+
+wick_status wick_profile(int32_t enable)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (enable) {
+        prof_flush_locked();
+        g_prof_done.clear();
+    }
+    g_prof_on = enable != 0;
+    return WICK_OK;
+}
+
+wick_status wick_profile_read(const char *kernel, int64_t *launches, double *total_ms)
+{
+    if (!kernel) return fail(WICK_EINVAL, "wick_profile_read: null name");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_flush_locked();
+    auto it = g_prof_done.find(kernel);
+    if (launches) *launches = it == g_prof_done.end() ? 0 : it->second.first;
+    if (total_ms) *total_ms = it == g_prof_done.end() ? 0.0 : it->second.second;
+    return WICK_OK;
+}
+
+const char *wick_last_error(void) { return g_last_error.c_str(); }
+
+const char *wick_version(void) { return "wick-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal data structures shared by the planner, the C ABI and the kernels'
+// host-side launchers. Not part of the public interface.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/wick.h"
+
+namespace wick {
+
+constexpr int kMaxA = 5;          // nucleons per operator
+constexpr int kBlockLen = 792;    // compact antisymmetrised block: 66 pairs x 12
+constexpr int kMaxTrials = 4;     // identity tests per term
+constexpr int kMaxKindsPerGroup = 5;  // 12*5 = 60 <= 64 MFMA rows (4 tiles of 16)
+constexpr int kMaxRows = 8;       // E rows per group
+constexpr int kMaxRowTerms = 16;  // (j2, j3) terms per E row
+constexpr int kMaxAop = 2;        // (j1, a) terms per (kind, row)
+
+struct GInt {
+    int64_t re = 0, im = 0;
+};
+
+struct KindDef {
+    int flav[3] = {0, 0, 0};
+    std::vector<std::array<int8_t, 3>> j;
+    std::vector<GInt> w;
+};
+
+// One E row: E_r(x)[i2, i3] = sum_t w_t S_g(x)[j2_t, i2] S_f(x)[j3_t, i3].
+struct ERow {
+    std::vector<std::array<int8_t, 2>> jj;  // (j2, j3)
+    std::vector<int8_t> w;                  // small integer weights
+};
+
+// Kinds of one flavor pattern (f, g, f) whose weights factor through common
+// E rows: w_k(j1, j2, j3) = sum_r a_k(j1, r) E_r(j2, j3).
+struct EGroup {
+    int f = 0, g = 1;
+    std::vector<ERow> rows;
+    std::vector<int> kinds;  // block-kind indices
+    // aop[(kk * R + r) * kMaxAop + e] = {j1, a}; a == 0 marks an unused entry
+    std::vector<std::array<int8_t, 2>> aop;
+};
+
+struct DeviceTable {
+    int device = -1;
+    void *kidx = nullptr;   // uint16 [A][n_terms]
+    void *coef = nullptr;   // double [n_terms] (real) or [n_terms][2]
+};
+
+struct wick_plan_impl;
+
+}  // namespace wick
+
+struct wick_plan_s {
+    int A = 0;
+    std::vector<wick::KindDef> kinds;   // block kinds (used by sink patterns)
+    std::vector<wick::EGroup> egroups;
+    int64_t n_terms = 0;
+    std::vector<uint16_t> kidx;         // [A][n_terms]
+    std::vector<double> coef_re, coef_im;
+    bool coef_real = true;
+    int64_t n_enumerated = 0, n_groups = 0;
+    double bound = 0.0, scale = 1.0;
+    // device copies of the table, one per device
+    std::mutex dev_mu;
+    std::vector<wick::DeviceTable> dev;
+    ~wick_plan_s();
+};
+
+namespace wick {
+
+void set_error(const std::string &msg);
+wick_status fail(wick_status st, const std::string &msg);
+
+// planner (plan.cpp)
+wick_status build_plan(const wick_nucleus_desc *d, wick_plan_t *out);
+void factor_kinds(wick_plan_s *p);  // fills p->egroups
+wick_status save_plan(const wick_plan_s *p, const char *path);
+wick_status load_plan(const char *path, wick_plan_t *out);
+
+// built-in operators (nuclei.cpp)
+wick_status std_plan(const char *name, int32_t J, wick_plan_t *out);
+
+// device-table release (api.cpp)
+void release_device_tables(wick_plan_s *p);
+
+}  // namespace wick

@@ -1,0 +1,324 @@
+// HIP kernels for gfx950 (MI355X): baryon blocks on MFMA and the FP64 Wick-term sum.
+//
+// Block build (Eq. 2.4, App. D). For a group of kinds sharing their diquark
+// rows (same flavors (f, g, f) and the same eps * (C g5 P) structure),
+//   Braw_k[i1, (i2,i3)] = sum_x sum_r Aop_k(x, r)[i1] * E_r(x)[(i2,i3)],
+//   E_r(x)[i2,i3]      = sum_t w_t S_g(x)[j2_t, i2] S_f(x)[j3_t, i3]   (VALU),
+//   Aop_k(x, r)[i1]    = sum_e a_e S_f(x)[j1_e, i1]                     (a row of S_f),
+// i.e. a complex GEMM with M = 144 (i2, i3), N = 12 per kind (i1), and
+// K = R per site summed over all sites. It runs on v_mfma_f64_16x16x4f64:
+// the A operand is E (lane l: column n = 16*tile + l%16, site l/16), the B
+// operand is Aop (lane l: site l/16, row m = 16*mtile + l%16 -> (kind, i1)),
+// so each MFMA contracts four sites at once. Complex products take four
+// real MFMAs (re*re - im*im, re*im + im*re).
+//
+// Sites are split into chunks (split-K); each wave writes its chunk's partial
+// block and a second kernel sums the chunks in a fixed order and
+// antisymmetrises the two same-flavor slots (Eq. 2.4), so results are
+// bitwise repeatable.
+//
+// Term sum (Eq. 2.6, App. D): one workgroup per (configuration, time slice,
+// slice of the term table); the blocks of its (cfg, t) sit in LDS, each lane
+// gathers A entries per term, multiplies in FP64 and accumulates; a fixed
+// shuffle/LDS tree reduces the workgroup and a second kernel sums the slices
+// in order.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace wick {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct cplx {
+    double x, y;
+};
+
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+
+template <typename TIn>
+__device__ __forceinline__ cplx ld(const TIn *p)
+{
+    return {(double)p->x, (double)p->y};
+}
+
+// Block id remapped so that consecutive logical ids run on one XCD
+// (hardware places block b on XCD b % 8). Requires gridDim.x % 8 == 0.
+__device__ __forceinline__ int xcd_block()
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+constexpr int kMT = 4;  // maximum MFMA m-tiles per group (5 kinds x 12 rows <= 64)
+
+template <typename TIn>
+__global__ __launch_bounds__(256) void blocks_f64_kernel(
+    const TIn *__restrict__ Su, const TIn *__restrict__ Sd, const EGroupDev *__restrict__ groups,
+    int n_units, int64_t V, int chunk_sites, int n_chunks, int K, int64_t n_waves_total,
+    double2 *__restrict__ partial)
+{
+    const int64_t wave =
+        __builtin_amdgcn_readfirstlane((int64_t)xcd_block() * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    if (wave >= n_waves_total) return;
+    const int unit = (int)(wave % n_units);
+    const int64_t rest = wave / n_units;
+    const int chunk = (int)(rest % n_chunks);
+    const int64_t ct = rest / n_chunks;
+    const int gi = unit / kNTiles, nt = unit % kNTiles;
+    const EGroupDev &G = groups[gi];
+    const int R = G.R, nk = G.nk, MT = G.mt;
+
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const int n = nt * 16 + c, i2 = n / 12, i3 = n % 12;
+    const TIn *Sf = (G.f == 0 ? Su : Sd) + ct * V * 144;
+    const TIn *Sg = (G.g == 0 ? Su : Sd) + ct * V * 144;
+
+    int kk_m[kMT], i1_m[kMT];
+#pragma unroll
+    for (int mt = 0; mt < kMT; ++mt) {
+        const int m = mt * 16 + c;
+        kk_m[mt] = m / 12;
+        i1_m[mt] = m % 12;
+    }
+
+    d4 acc[kMT][2];
+#pragma unroll
+    for (int mt = 0; mt < kMT; ++mt) acc[mt][0] = acc[mt][1] = d4{0, 0, 0, 0};
+
+    const int64_t x0 = (int64_t)chunk * chunk_sites;
+    const int64_t x1 = x0 + chunk_sites < V ? x0 + chunk_sites : V;
+    for (int64_t xs = x0; xs < x1; xs += 4) {
+        const int64_t x = xs + q;
+        const bool ok = x < x1;
+        const TIn *sf = Sf + (ok ? x : x0) * 144;
+        const TIn *sg = Sg + (ok ? x : x0) * 144;
+        for (int r = 0; r < R; ++r) {
+            cplx E = {0.0, 0.0};
+            const int nterm = G.nterm[r];
+            for (int t = 0; t < nterm; ++t) {
+                const cplx a = ld(sg + G.j2[r][t] * 12 + i2);
+                const cplx b = ld(sf + G.j3[r][t] * 12 + i3);
+                const cplx p = cmul(a, b);
+                const double w = (double)G.w[r][t];
+                E.x += w * p.x;
+                E.y += w * p.y;
+            }
+            if (!ok) E = {0.0, 0.0};
+#pragma unroll
+            for (int mt = 0; mt < kMT; ++mt) {
+                if (mt >= MT) break;
+                cplx Ao = {0.0, 0.0};
+                const int kk = kk_m[mt];
+                if (kk < nk) {
+#pragma unroll
+                    for (int e = 0; e < kMaxAop; ++e) {
+                        const int a = G.aa[kk][r][e];
+                        if (a) {
+                            const cplx s = ld(sf + G.aj1[kk][r][e] * 12 + i1_m[mt]);
+                            Ao.x += a * s.x;
+                            Ao.y += a * s.y;
+                        }
+                    }
+                }
+                acc[mt][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(E.x, Ao.x, acc[mt][0], 0, 0, 0);
+                acc[mt][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(E.y, -Ao.y, acc[mt][0], 0, 0, 0);
+                acc[mt][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(E.x, Ao.y, acc[mt][1], 0, 0, 0);
+                acc[mt][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(E.y, Ao.x, acc[mt][1], 0, 0, 0);
+            }
+        }
+    }
+    // D layout of the 16x16 f64 MFMA: lane l, item v -> row 4*(l/16)+v, column l%16.
+    double2 *P = partial + (ct * n_chunks + chunk) * (int64_t)K * 1728;
+#pragma unroll
+    for (int mt = 0; mt < kMT; ++mt) {
+        if (mt >= MT) break;
+        const int kk = kk_m[mt];
+        if (kk >= nk) continue;
+        const int kind = G.kind_out[kk];
+        double2 *row = P + ((int64_t)kind * 12 + i1_m[mt]) * 144 + nt * 16 + 4 * q;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) row[v] = double2{acc[mt][0][v], acc[mt][1][v]};
+    }
+}
+
+// Sum the chunks in order and antisymmetrise: B[c] = sum_ch P[i1][i2,i3] - P[i3][i2,i1].
+__global__ __launch_bounds__(256) void blocks_reduce_kernel(const double2 *__restrict__ partial, int n_chunks,
+                                                            int K, int64_t n_out, double2 *__restrict__ B)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_out) return;
+    const int per = K * 792;
+    const int64_t ct = idx / per;
+    const int e = (int)(idx % per);
+    const int kind = e / 792, cc = e % 792, pr = cc / 12, i2 = cc % 12;
+    int i3 = 1;
+    while ((i3 + 1) * i3 / 2 <= pr) ++i3;
+    const int i1 = pr - i3 * (i3 - 1) / 2;
+    const double2 *P = partial + ct * n_chunks * (int64_t)K * 1728 + (int64_t)kind * 1728;
+    const int oa = i1 * 144 + i2 * 12 + i3, ob = i3 * 144 + i2 * 12 + i1;
+    double sx = 0.0, sy = 0.0;
+    for (int ch = 0; ch < n_chunks; ++ch) {
+        const double2 a = P[(int64_t)ch * K * 1728 + oa];
+        const double2 b = P[(int64_t)ch * K * 1728 + ob];
+        sx += a.x - b.x;
+        sy += a.y - b.y;
+    }
+    B[idx] = double2{sx, sy};
+}
+
+template <int A, bool REAL, bool LDSB>
+__global__ __launch_bounds__(256) void contract_kernel(const double2 *__restrict__ B, const uint16_t *__restrict__ kidx,
+                                                       const double *__restrict__ coef, int64_t N, int K, int n_ct,
+                                                       int n_slices, int64_t slice_len, double2 *__restrict__ partial)
+{
+    extern __shared__ double2 sB[];
+    __shared__ double red[2][4];
+    const int lb = xcd_block();
+    if (lb >= n_ct * n_slices) return;
+    const int ct = lb / n_slices, slice = lb % n_slices;
+    const double2 *Bc = B + (int64_t)ct * K * 792;
+    const double2 *src = Bc;
+    if (LDSB) {
+        for (int i = threadIdx.x; i < K * 792; i += blockDim.x) sB[i] = Bc[i];
+        __syncthreads();
+        src = sB;
+    }
+    const int64_t n0 = (int64_t)slice * slice_len;
+    const int64_t n1 = n0 + slice_len < N ? n0 + slice_len : N;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+        double2 p = src[kidx[n]];
+#pragma unroll
+        for (int a = 1; a < A; ++a) {
+            const double2 b = src[kidx[(int64_t)a * N + n]];
+            p = double2{p.x * b.x - p.y * b.y, p.x * b.y + p.y * b.x};
+        }
+        if (REAL) {
+            const double c = coef[n];
+            ar += c * p.x;
+            ai += c * p.y;
+        } else {
+            const double cr = coef[2 * n], ci = coef[2 * n + 1];
+            ar += cr * p.x - ci * p.y;
+            ai += cr * p.y + ci * p.x;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        ar += __shfl_xor(ar, off);
+        ai += __shfl_xor(ai, off);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = ar;
+        red[1][w] = ai;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sr = 0.0, si = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            sr += red[0][i];
+            si += red[1][i];
+        }
+        partial[(int64_t)ct * n_slices + slice] = double2{sr, si};
+    }
+}
+
+__global__ void contract_finalize_kernel(const double2 *__restrict__ partial, int n_ct, int n_slices,
+                                         double2 *__restrict__ C)
+{
+    const int ct = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ct >= n_ct) return;
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < n_slices; ++s) {
+        const double2 v = partial[(int64_t)ct * n_slices + s];
+        sr += v.x;
+        si += v.y;
+    }
+    C[ct] = double2{sr, si};
+}
+
+int round8(int64_t n) { return (int)((n + 7) / 8 * 8); }
+
+}  // namespace
+
+hipError_t launch_blocks(const BlockLaunch &L, hipStream_t s)
+{
+    const int n_units = L.n_groups * kNTiles;
+    const int64_t n_ct = (int64_t)L.n_cfg * L.T;
+    const int64_t waves = (int64_t)n_units * L.n_chunks * n_ct;
+    const int wpb = 4;
+    const int64_t blocks = round8((waves + wpb - 1) / wpb);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    Probe pr("blocks", s);
+    if (L.dtype == 0)
+        hipLaunchKernelGGL(blocks_f64_kernel<double2>, dim3((unsigned)blocks), dim3(64 * wpb), 0, s,
+                           (const double2 *)L.Su, (const double2 *)L.Sd, L.groups, n_units, L.V, L.chunk_sites,
+                           L.n_chunks, L.K, waves, (double2 *)L.partial);
+    else
+        hipLaunchKernelGGL(blocks_f64_kernel<float2>, dim3((unsigned)blocks), dim3(64 * wpb), 0, s,
+                           (const float2 *)L.Su, (const float2 *)L.Sd, L.groups, n_units, L.V, L.chunk_sites,
+                           L.n_chunks, L.K, waves, (double2 *)L.partial);
+    pr.stop();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n_out = n_ct * L.K * 792;
+    Probe pr2("blocks_reduce", s);
+    hipLaunchKernelGGL(blocks_reduce_kernel, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, s,
+                       (const double2 *)L.partial, L.n_chunks, L.K, n_out, (double2 *)L.B);
+    pr2.stop();
+    return hipGetLastError();
+}
+
+size_t contract_lds_bytes(int K) { return (size_t)K * 792 * sizeof(double2); }
+
+namespace {
+template <int A, bool REAL>
+void dispatch_lds(const ContractLaunch &L, hipStream_t s, unsigned blocks, bool lds)
+{
+    if (lds) {
+        // LDS above the 64 KiB default needs an explicit opt-in per kernel
+        static const hipError_t attr = hipFuncSetAttribute(
+            (const void *)contract_kernel<A, REAL, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
+        (void)attr;
+        hipLaunchKernelGGL((contract_kernel<A, REAL, true>), dim3(blocks), dim3(256), contract_lds_bytes(L.K), s,
+                           (const double2 *)L.B, L.kidx, L.coef, L.N, L.K, L.n_ct, L.n_slices, L.slice_len,
+                           (double2 *)L.partial);
+    } else
+        hipLaunchKernelGGL((contract_kernel<A, REAL, false>), dim3(blocks), dim3(256), 0, s, (const double2 *)L.B,
+                           L.kidx, L.coef, L.N, L.K, L.n_ct, L.n_slices, L.slice_len, (double2 *)L.partial);
+}
+template <int A>
+void dispatch_real(const ContractLaunch &L, hipStream_t s, unsigned blocks, bool lds)
+{
+    if (L.coef_real) dispatch_lds<A, true>(L, s, blocks, lds);
+    else dispatch_lds<A, false>(L, s, blocks, lds);
+}
+}  // namespace
+
+hipError_t launch_contract(const ContractLaunch &L, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)round8((int64_t)L.n_ct * L.n_slices);
+    const bool lds = contract_lds_bytes(L.K) <= 160 * 1024 - 256;
+    Probe pr("contract", s);
+    switch (L.A) {
+    case 1: dispatch_real<1>(L, s, blocks, lds); break;
+    case 2: dispatch_real<2>(L, s, blocks, lds); break;
+    case 3: dispatch_real<3>(L, s, blocks, lds); break;
+    case 4: dispatch_real<4>(L, s, blocks, lds); break;
+    case 5: dispatch_real<5>(L, s, blocks, lds); break;
+    default: return hipErrorInvalidValue;
+    }
+    pr.stop();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    Probe pr2("contract_finalize", s);
+    hipLaunchKernelGGL(contract_finalize_kernel, dim3((L.n_ct + 255) / 256), dim3(256), 0, s,
+                       (const double2 *)L.partial, L.n_ct, L.n_slices, (double2 *)L.C);
+    pr2.stop();
+    return hipGetLastError();
+}
+
+}  // namespace wick

@@ -1,0 +1,67 @@
+// Device-side descriptors and host launchers of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace wick {
+
+// One E group as the block kernel reads it (uniform per wave).
+struct EGroupDev {
+    int32_t f, g, R, nk, mt;
+    int32_t kind_out[kMaxKindsPerGroup];
+    int32_t nterm[kMaxRows];
+    int8_t j2[kMaxRows][kMaxRowTerms];
+    int8_t j3[kMaxRows][kMaxRowTerms];
+    int8_t w[kMaxRows][kMaxRowTerms];
+    int8_t aj1[kMaxKindsPerGroup][kMaxRows][kMaxAop];
+    int8_t aa[kMaxKindsPerGroup][kMaxRows][kMaxAop];
+};
+
+constexpr int kNTiles = 9;  // 144 (i2, i3) columns = 9 MFMA tiles of 16
+
+struct BlockLaunch {
+    const void *Su, *Sd;
+    int dtype;               // 0 = complex128, 1 = complex64
+    int prec;                // wick_precision
+    const EGroupDev *groups; // device
+    int n_groups;
+    int64_t V;
+    int T, n_cfg, K;
+    int chunk_sites, n_chunks;
+    double *partial;         // [n_cfg*T][n_chunks][K][12][144][2]
+    double *B;               // [n_cfg*T][K][792][2]
+};
+
+hipError_t launch_blocks(const BlockLaunch &L, hipStream_t s);
+
+struct ContractLaunch {
+    const double *B;         // [n_ct][K][792][2]
+    const uint16_t *kidx;    // [A][N]
+    const double *coef;      // [N] or [N][2]
+    bool coef_real;
+    int A, K;
+    int64_t N;
+    int n_ct;
+    int n_slices;
+    int64_t slice_len;
+    double *partial;         // [n_ct][n_slices][2]
+    double *C;               // [n_ct][2]
+};
+
+hipError_t launch_contract(const ContractLaunch &L, hipStream_t s);
+
+size_t contract_lds_bytes(int K);
+
+// Optional per-kernel event timing (api.hip). A Probe records a start event
+// on construction and a stop event on stop() when profiling is enabled.
+struct Probe {
+    Probe(const char *name, hipStream_t s);
+    void stop();
+    const char *name;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace wick

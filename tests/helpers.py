@@ -1,0 +1,61 @@
+"""Shared test helpers: operator conversion and table evaluation on the CPU."""
+import re
+import os
+
+import numpy as np
+
+import oracle
+from oracle import operators as ops
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def pair_index(i1, i3):
+    return i3 * (i3 - 1) // 2 + i1
+
+
+def compact(Bfull):
+    """[..., 12, 12, 12] antisymmetric block -> [..., 792] (c = pair(i1<i3)*12 + i2)."""
+    out = np.zeros(Bfull.shape[:-3] + (792,), dtype=Bfull.dtype)
+    for i3 in range(12):
+        for i1 in range(i3):
+            for i2 in range(12):
+                out[..., pair_index(i1, i3) * 12 + i2] = Bfull[..., i1, i2, i3]
+    return out
+
+
+def oracle_compact_blocks(op, kind_order, Su_t, Sd_t):
+    """Oracle blocks in the form of Eq. 2.4 (antisymmetrised), compact, in the plan's kind order."""
+    return np.stack([compact(oracle.block_eq24(op.kinds[k], Su_t, Sd_t)) for k in kind_order])
+
+
+def eval_table(kidx, coef, Bc):
+    """sum_n coef_n prod_a Bc.flat[kidx[a, n]] and sum_n |coef_n prod_a ...| (FP64, numpy)."""
+    flat = Bc.reshape(-1)
+    prod = np.ones(kidx.shape[1], dtype=np.complex128)
+    for a in range(kidx.shape[0]):
+        prod = prod * flat[kidx[a].astype(np.int64)]
+    terms = coef * prod
+    return terms.sum(), np.abs(terms).sum()
+
+
+def to_wick(op):
+    """oracle Operator -> the binding's plan() arguments (the same exact integers)."""
+    kinds = [(k.flavors, k.w) for k in op.kinds]
+    return dict(A=op.A, kinds=kinds, snk=op.snk, src=op.src, scale=op.scale)
+
+
+def sink_kind_order(op):
+    """Kinds used at the sink, in order of first use (the planner's block-kind order)."""
+    order = []
+    for p, _ in op.snk:
+        for k in p:
+            if k not in order:
+                order.append(k)
+    return order
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "wick.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(wick_[a-z_]+)\s*\(", txt)))

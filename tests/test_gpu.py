@@ -1,0 +1,184 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bounds (per time slice): |C_gpu - C_oracle| <= 1e-12 * sum_n |term_n| for the
+FP64 path, with sum |term_n| taken over the deduplicated table evaluated
+with the oracle's blocks. Blocks: |B_gpu - B_oracle| <= 1e-12 * max |B|.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import wick_inputs as wi
+from oracle import operators as ops
+from tests.helpers import eval_table, oracle_compact_blocks, sink_kind_order
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def W():
+    import paper_2411_08962_amd as w
+    return w
+
+
+def props(wid, n_cfg, dims, dtype=np.complex128):
+    """Host and device propagators [n_cfg, T, Z, Y, X, 12, 12] for both flavors."""
+    torch = _torch()
+    hu = np.stack([wi.propagator(wid, c, 0, dims, dtype) for c in range(n_cfg)])
+    hd = np.stack([wi.propagator(wid, c, 1, dims, dtype) for c in range(n_cfg)])
+    return hu, hd, torch.from_numpy(hu).cuda(), torch.from_numpy(hd).cuda()
+
+
+def oracle_blocks(op, hu, hd, cfg, t):
+    return oracle_compact_blocks(op, sink_kind_order(op), hu[cfg, t].astype(np.complex128),
+                                 hd[cfg, t].astype(np.complex128))
+
+
+def check_blocks(op, B, hu, hd, ts, cfg=0):
+    for t in ts:
+        ref = oracle_blocks(op, hu, hd, cfg, t)
+        got = B[cfg, t, ..., 0] + 1j * B[cfg, t, ..., 1]
+        err = np.max(np.abs(got - ref))
+        assert err <= TOL64 * np.max(np.abs(ref)), (t, err, np.max(np.abs(ref)))
+
+
+def check_C(op, pl, C, hu, hd, ts, cfg=0, tol=TOL64):
+    kidx, coef = pl.table()
+    worst = 0.0
+    for n, t in enumerate(ts):
+        Bc = oracle_blocks(op, hu, hd, cfg, t)
+        tab, mag = eval_table(kidx, coef, Bc)
+        ref = op.scale * oracle.sum_dp(op, oracle.blocks_raw(op, hu[cfg, t].astype(np.complex128),
+                                                              hd[cfg, t].astype(np.complex128)))
+        got = C[cfg, t, 0] + 1j * C[cfg, t, 1]
+        assert abs(tab - ref) <= 1e-12 * mag              # the table is right (host)
+        rel = abs(got - ref) / mag
+        worst = max(worst, rel)
+        assert rel <= tol, (t, got, ref, mag)
+    return worst
+
+
+# ----------------------------------------------------------------- blocks
+def test_blocks_deuteron_4x4x4x8():
+    w = W()
+    pl = w.plan_std("2H")
+    hu, hd, du, dd = props(1, 1, (4, 4, 4, 8))
+    B = w.blocks(pl, du, dd).cpu().numpy()
+    check_blocks(ops.deuteron(), B, hu, hd, range(8))
+
+
+def test_blocks_ragged_volume_and_c64():
+    # V = 30 is not a multiple of the 4 sites per MFMA step nor of a chunk
+    w = W()
+    pl = w.plan_std("3He")
+    hu, hd, du, dd = props(2, 1, (5, 3, 2, 2), np.complex64)
+    B = w.blocks(pl, du, dd).cpu().numpy()
+    check_blocks(ops.helium3(), B, hu, hd, range(2))
+
+
+def test_blocks_identity_propagator_closed_form():
+    # S = 1 at every site: B = V * (w(i1,i2,i3) - w(i3,i2,i1)) exactly
+    torch = _torch()
+    w = W()
+    pl = w.plan_std("2H")
+    dims = (3, 2, 2, 1)
+    V = 12
+    S = torch.eye(12, dtype=torch.complex128).expand(1, 1, 2, 2, 3, 12, 12).contiguous().cuda()
+    B = w.blocks(pl, S, S).cpu().numpy()
+    op = ops.deuteron()
+    from tests.helpers import compact
+    for k_plan, k in enumerate(sink_kind_order(op)):
+        Wt = np.zeros((12, 12, 12))
+        for j1, j2, j3, a, b in op.kinds[k].w:
+            Wt[j1, j2, j3] += a
+        ref = compact(V * (Wt - Wt.transpose(2, 1, 0)))
+        assert np.array_equal(B[0, 0, k_plan, :, 0], ref)
+        assert np.all(B[0, 0, k_plan, :, 1] == 0)
+
+
+# ------------------------------------------------------------- contraction
+def test_contract_on_oracle_blocks():
+    torch = _torch()
+    w = W()
+    op = ops.helium3()
+    pl = w.plan_std("3He")
+    hu, hd, _, _ = props(3, 1, (3, 1, 1, 2))
+    Bc = np.stack([oracle_blocks(op, hu, hd, 0, t) for t in range(2)])[None]
+    Bd = torch.from_numpy(np.stack([Bc.real, Bc.imag], -1)).contiguous().cuda()
+    C = w.contract(pl, Bd).cpu().numpy()
+    kidx, coef = pl.table()
+    for t in range(2):
+        tab, mag = eval_table(kidx, coef, Bc[0, t])
+        assert abs(C[0, t, 0] + 1j * C[0, t, 1] - tab) <= TOL64 * mag
+
+
+# --------------------------------------------------------------- end to end
+def test_deuteron_config_4x4x4x8_all_t():
+    w = W()
+    pl = w.plan_std("2H")
+    hu, hd, du, dd = props(1, 1, (4, 4, 4, 8))
+    C = w.contract(pl, w.blocks(pl, du, dd)).cpu().numpy()
+    check_C(ops.deuteron(), pl, C, hu, hd, range(8))
+
+
+@pytest.mark.parametrize("name", ["3He", "3H"])
+def test_three_nucleon_small(name):
+    w = W()
+    pl = w.plan_std(name)
+    hu, hd, du, dd = props(4, 1, (2, 2, 2, 3))
+    C = w.contract(pl, w.blocks(pl, du, dd)).cpu().numpy()
+    check_C(ops.by_name(name), pl, C, hu, hd, range(3))
+
+
+def test_two_configurations_and_determinism():
+    w = W()
+    pl = w.plan_std("2H")
+    hu, hd, du, dd = props(5, 2, (3, 3, 2, 2))
+    C1 = w.contract(pl, w.blocks(pl, du, dd)).cpu().numpy()
+    C2 = w.contract(pl, w.blocks(pl, du, dd)).cpu().numpy()
+    assert np.array_equal(C1, C2)  # bitwise repeatable
+    for cfg in range(2):
+        check_C(ops.deuteron(), pl, C1, hu, hd, range(2), cfg=cfg)
+
+
+def test_sparse_helium4_end_to_end():
+    w = W()
+    from tests.helpers import to_wick
+    for s in range(200):
+        op = ops.sparsify(ops.helium4(), 6, np.random.default_rng(s), keep_patterns=4)
+        if oracle.source_group_count(op) > 0:
+            break
+    pl = w.plan(**to_wick(op))
+    hu, hd, du, dd = props(6, 1, (2, 2, 1, 2))
+    C = w.contract(pl, w.blocks(pl, du, dd)).cpu().numpy()
+    check_C(op, pl, C, hu, hd, range(2))
+
+
+def test_correlator_entry_point_mixed_nuclei():
+    w = W()
+    plans = [w.plan_std("2H"), w.plan_std("3He")]
+    hu, hd, du, dd = props(7, 2, (2, 2, 2, 2))
+    C = w.correlator(plans, [(0, 1), (1, 0)], du, dd).cpu().numpy()
+    check_C(ops.deuteron(), plans[0], C[0:1], hu[1:2], hd[1:2], range(2))
+    check_C(ops.helium3(), plans[1], C[1:2], hu[0:1], hd[0:1], range(2))
+
+
+# -------------------------------------------------- full-size workload, sampled
+def test_helium3_16cubed_x32_sampled():
+    """The benchmark workload (3He on 16^3 x 32, complex128, FP64), at its full
+    size and in the launch configuration bench.py times; the oracle checks
+    sampled time slices."""
+    w = W()
+    pl = w.plan_std("3He")
+    hu, hd, du, dd = props(2, 1, (16, 16, 16, 32))
+    B = w.blocks(pl, du, dd)
+    C = w.contract(pl, B).cpu().numpy()
+    Bn = B.cpu().numpy()
+    check_blocks(ops.helium3(), Bn, hu, hd, [31])
+    check_C(ops.helium3(), pl, C, hu, hd, [0, 31])
