@@ -129,7 +129,8 @@ __global__ __launch_bounds__(256) void blocks_f64_kernel(
             }
         }
     }
-    // D layout of the 16x16 f64 MFMA: lane l, item v -> row 4*(l/16)+v, column l%16.
+    // D layout of the 16x16x4 f64 MFMA (measured on gfx950): lane l, item v ->
+    // row 4*v + l/16, column l%16. (The f32 variant uses row 4*(l/16) + v.)
     double2 *P = partial + (ct * n_chunks + chunk) * (int64_t)K * 1728;
 #pragma unroll
     for (int mt = 0; mt < kMT; ++mt) {
@@ -137,9 +138,9 @@ __global__ __launch_bounds__(256) void blocks_f64_kernel(
         const int kk = kk_m[mt];
         if (kk >= nk) continue;
         const int kind = G.kind_out[kk];
-        double2 *row = P + ((int64_t)kind * 12 + i1_m[mt]) * 144 + nt * 16 + 4 * q;
+        double2 *row = P + ((int64_t)kind * 12 + i1_m[mt]) * 144 + nt * 16 + q;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) row[v] = double2{acc[mt][0][v], acc[mt][1][v]};
+        for (int v = 0; v < 4; ++v) row[4 * v] = double2{acc[mt][0][v], acc[mt][1][v]};
     }
 }
 
