@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -73,7 +74,9 @@ wick_status workspace(hipStream_t s, size_t bytes, void **out)
 // ---------------------------------------------------------- device tables
 struct DevPlan {
     int device = -1;
+    int n_tiles = 0, n_passes = 0;
     EGroupDev *groups = nullptr;
+    BlocksDesc *desc = nullptr;  // null when the staged kernel does not apply
     uint16_t *kidx = nullptr;
     double *coef = nullptr;
 };
@@ -138,6 +141,43 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
                     h.aa[k][r][u] = a[1];
                 }
         }
+    }
+    // the staged kernel's descriptor: groups packed into passes of at most
+    // kPassTiles m-tiles (first fit, largest groups first)
+    BlocksDesc bd;
+    std::memset(&bd, 0, sizeof(bd));
+    for (int pp = 0; pp < kMaxPasses; ++pp)
+        for (int t = 0; t < kPassTiles; ++t) bd.tile_group[pp][t] = -1;
+    bool staged = (int)hg.size() <= kMaxGroupsStaged;
+    int max_tiles = 0;
+    if (staged) {
+        bd.n_groups = (int)hg.size();
+        std::vector<int> order(hg.size());
+        for (size_t g = 0; g < hg.size(); ++g) order[g] = (int)g;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return hg[x].mt > hg[y].mt; });
+        for (int g : order) {
+            bd.groups[g] = hg[g];
+            if (hg[g].mt > kPassTiles) { staged = false; break; }
+            int pp = 0;
+            while (pp < bd.n_passes && bd.pass_tiles[pp] + hg[g].mt > kPassTiles) ++pp;
+            if (pp == kMaxPasses) { staged = false; break; }
+            if (pp == bd.n_passes) ++bd.n_passes;
+            bd.pass_groups[pp][bd.pass_ngroups[pp]++] = g;
+            for (int mt = 0; mt < hg[g].mt; ++mt) {
+                bd.tile_group[pp][bd.pass_tiles[pp]] = g;
+                bd.tile_mt[pp][bd.pass_tiles[pp]] = mt;
+                ++bd.pass_tiles[pp];
+            }
+            max_tiles = std::max(max_tiles, bd.pass_tiles[pp]);
+        }
+    }
+    if (staged) {
+        d.n_tiles = max_tiles;
+        d.n_passes = bd.n_passes;
+        if ((e = hipMalloc(&d.desc, sizeof(BlocksDesc))) != hipSuccess)
+            return fail(WICK_ENOMEM, std::string("plan upload hipMalloc: ") + hipGetErrorString(e));
+        if ((e = hipMemcpy(d.desc, &bd, sizeof(bd), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "plan upload hipMemcpy");
     }
     size_t nt = (size_t)p->n_terms;
     size_t coef_n = p->coef_real ? nt : 2 * nt;
@@ -228,6 +268,12 @@ wick_status do_blocks(wick_plan_s *p, const void *Su, const void *Sd, int dtype,
     L.prec = prec;
     L.groups = dp->groups;
     L.n_groups = (int)p->egroups.size();
+    L.desc = dp->desc;
+    L.n_tiles = dp->n_tiles;
+    L.n_passes = dp->n_passes;
+    // WICK_BLOCKS_KERNEL=generic selects the one-wave-per-tile kernel (tests use it)
+    if (const char *k = std::getenv("WICK_BLOCKS_KERNEL"))
+        if (std::strcmp(k, "generic") == 0) L.desc = nullptr;
     L.V = V;
     L.T = dims[3];
     L.n_cfg = n_cfg;
@@ -335,6 +381,7 @@ void release_device_tables(wick_plan_s *p)
         (void)hipSetDevice(d.device);
         (void)hipDeviceSynchronize();
         (void)hipFree(d.groups);
+        (void)hipFree(d.desc);
         (void)hipFree(d.kidx);
         (void)hipFree(d.coef);
     }

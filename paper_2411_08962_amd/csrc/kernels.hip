@@ -144,6 +144,150 @@ __global__ __launch_bounds__(256) void blocks_f64_kernel(
     }
 }
 
+// Staged variant: one workgroup of 9 waves per (cfg*T + t, site chunk); wave
+// w owns column tile w (16 of the 144 (i2, i3) columns) for every group, so
+// all waves share the sites' propagators, which are brought from HBM once
+// per workgroup with coalesced 16-byte loads into double-buffered LDS
+// (kSB sites per buffer; the next batch is loaded while this one is used).
+constexpr int kSB = 8;
+constexpr int kStagedThreads = 64 * kNTiles;
+
+template <typename TIn, int NT>
+__global__ __launch_bounds__(kStagedThreads) void blocks_f64_staged_kernel(
+    const TIn *__restrict__ Su, const TIn *__restrict__ Sd, const BlocksDesc *__restrict__ desc, int64_t V,
+    int chunk_sites, int n_chunks, int K, int n_work, double2 *__restrict__ partial)
+{
+    __shared__ double2 sbuf[2][kSB][2][144];
+    // E-row terms of the pass's groups: (j2*12) | (j3*12) << 8 | (w & 0xff) << 16
+    __shared__ int32_t s_et[kPassTiles][kMaxRows][kMaxRowTerms];
+    // per tile, row and column lane: two (offset j1*12 + i1, coefficient) entries of Aop
+    __shared__ int2 s_ao[NT][kMaxRows][16];
+    const int lb = xcd_block();
+    if (lb >= n_work) return;
+    const int pass = lb % desc->n_passes;
+    const int chunk = (lb / desc->n_passes) % n_chunks;
+    const int64_t ct = lb / desc->n_passes / n_chunks;
+    const int nt = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const int n = nt * 16 + c, i2 = n / 12, i3 = n % 12;
+    const int npg = desc->pass_ngroups[pass];
+    const int32_t *tgroup = desc->tile_group[pass];
+
+    // descriptors -> LDS (once per workgroup)
+    for (int e = threadIdx.x; e < kPassTiles * kMaxRows * kMaxRowTerms; e += kStagedThreads) {
+        const int gl = e / (kMaxRows * kMaxRowTerms), r = (e / kMaxRowTerms) % kMaxRows, t = e % kMaxRowTerms;
+        int32_t v = 0;
+        if (gl < npg) {
+            const EGroupDev &G = desc->groups[desc->pass_groups[pass][gl]];
+            if (r < G.R && t < G.nterm[r])
+                v = (G.j2[r][t] * 12) | ((G.j3[r][t] * 12) << 8) | (((int)G.w[r][t] & 0xff) << 16);
+        }
+        (&s_et[0][0][0])[e] = v;
+    }
+    for (int e = threadIdx.x; e < NT * kMaxRows * 16; e += kStagedThreads) {
+        const int t = e / (kMaxRows * 16), r = (e / 16) % kMaxRows, cc = e % 16;
+        int2 v = int2{0, 0};
+        const int g = tgroup[t];
+        if (g >= 0) {
+            const EGroupDev &G = desc->groups[g];
+            const int m = desc->tile_mt[pass][t] * 16 + cc, kk = m / 12, i1 = m % 12;
+            if (kk < G.nk && r < G.R) {
+                v.x = (G.aj1[kk][r][0] * 12 + i1) | ((int)G.aa[kk][r][0] << 16);
+                v.y = (G.aj1[kk][r][1] * 12 + i1) | ((int)G.aa[kk][r][1] << 16);
+            }
+        }
+        (&s_ao[0][0][0])[e] = v;
+    }
+
+    d4 acc[NT][2];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t][0] = acc[t][1] = d4{0, 0, 0, 0};
+
+    const int64_t x0 = (int64_t)chunk * chunk_sites;
+    const int64_t x1 = x0 + chunk_sites < V ? x0 + chunk_sites : V;
+    const int nb = (int)((x1 - x0 + kSB - 1) / kSB);
+    const TIn *base[2] = {Su + ct * V * 144, Sd + ct * V * 144};
+    // each thread moves kPer of the kSB*2*144 entries of a batch
+    constexpr int kPer = kSB * 2 * 144 / kStagedThreads;
+    double2 stage[kPer];
+    auto load = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = threadIdx.x + u * kStagedThreads;     // [site][flavor][144]
+            const int s = e / 288, fl = (e / 144) & 1, j = e % 144;
+            const int64_t x = x0 + (int64_t)b * kSB + s;
+            if (x < x1) {
+                const TIn v = base[fl][x * 144 + j];
+                stage[u] = double2{(double)v.x, (double)v.y};
+            } else {
+                stage[u] = double2{0.0, 0.0};
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) (&sbuf[buf][0][0][0])[threadIdx.x + u * kStagedThreads] = stage[u];
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int b = 0; b < nb; ++b) {
+        const int cur = b & 1;
+        if (b + 1 < nb) load(b + 1);
+        for (int st = 0; st < kSB / 4; ++st) {
+            const int s = st * 4 + q;
+            // sites past the end were stored as zeros: their E and Aop vanish
+            for (int gl = 0; gl < npg; ++gl) {
+                const int g = desc->pass_groups[pass][gl];
+                const EGroupDev &G = desc->groups[g];
+                const double2 *sf = sbuf[cur][s][G.f];
+                const double2 *sg = sbuf[cur][s][G.g];
+                const double2 *sgi = sg + i2, *sfi = sf + i3;
+                for (int r = 0; r < G.R; ++r) {
+                    double ex = 0.0, ey = 0.0;
+                    const int nterm = G.nterm[r];
+                    const int32_t *et = s_et[gl][r];
+#pragma unroll 4
+                    for (int t = 0; t < nterm; ++t) {
+                        const int32_t pk = et[t];
+                        const double2 a = sgi[pk & 0xff];
+                        const double2 bb = sfi[(pk >> 8) & 0xff];
+                        const double w = (double)(int8_t)(pk >> 16);
+                        ex += w * (a.x * bb.x - a.y * bb.y);
+                        ey += w * (a.x * bb.y + a.y * bb.x);
+                    }
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        if (tgroup[t] != g) continue;
+                        const int2 ao = s_ao[t][r][c];
+                        const double2 v0 = sf[ao.x & 0xffff], v1 = sf[ao.y & 0xffff];
+                        const double a0 = (double)(ao.x >> 16), a1 = (double)(ao.y >> 16);
+                        const double ax = a0 * v0.x + a1 * v1.x, ay = a0 * v0.y + a1 * v1.y;
+                        acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, ax, acc[t][0], 0, 0, 0);
+                        acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, ay, acc[t][1], 0, 0, 0);
+                        acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey, -ay, acc[t][0], 0, 0, 0);
+                        acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey, ax, acc[t][1], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        if (b + 1 < nb) store(cur ^ 1);
+        __syncthreads();
+    }
+    double2 *P = partial + (ct * n_chunks + chunk) * (int64_t)K * 1728;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (tgroup[t] < 0) continue;
+        const EGroupDev &G = desc->groups[tgroup[t]];
+        const int m = desc->tile_mt[pass][t] * 16 + c, kk = m / 12, i1 = m % 12;
+        if (kk >= G.nk) continue;
+        const int kind = G.kind_out[kk];
+        double2 *row = P + ((int64_t)kind * 12 + i1) * 144 + nt * 16 + q;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) row[4 * v] = double2{acc[t][0][v], acc[t][1][v]};
+    }
+}
+
 // Sum the chunks in order and antisymmetrise: B[c] = sum_ch P[i1][i2,i3] - P[i3][i2,i1].
 __global__ __launch_bounds__(256) void blocks_reduce_kernel(const double2 *__restrict__ partial, int n_chunks,
                                                             int K, int64_t n_out, double2 *__restrict__ B)
@@ -249,19 +393,41 @@ hipError_t launch_blocks(const BlockLaunch &L, hipStream_t s)
 {
     const int n_units = L.n_groups * kNTiles;
     const int64_t n_ct = (int64_t)L.n_cfg * L.T;
-    const int64_t waves = (int64_t)n_units * L.n_chunks * n_ct;
-    const int wpb = 4;
-    const int64_t blocks = round8((waves + wpb - 1) / wpb);
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     Probe pr("blocks", s);
-    if (L.dtype == 0)
-        hipLaunchKernelGGL(blocks_f64_kernel<double2>, dim3((unsigned)blocks), dim3(64 * wpb), 0, s,
-                           (const double2 *)L.Su, (const double2 *)L.Sd, L.groups, n_units, L.V, L.chunk_sites,
-                           L.n_chunks, L.K, waves, (double2 *)L.partial);
-    else
-        hipLaunchKernelGGL(blocks_f64_kernel<float2>, dim3((unsigned)blocks), dim3(64 * wpb), 0, s,
-                           (const float2 *)L.Su, (const float2 *)L.Sd, L.groups, n_units, L.V, L.chunk_sites,
-                           L.n_chunks, L.K, waves, (double2 *)L.partial);
+    if (L.desc) {
+        const int64_t work = n_ct * L.n_chunks * L.n_passes;
+        if (work > 0x7ffffff0LL) return hipErrorInvalidValue;
+        const unsigned blocks = (unsigned)round8(work);
+        switch (L.n_tiles) {
+#define WICK_STAGED(NTV)                                                                                          \
+    case NTV:                                                                                                     \
+        if (L.dtype == 0)                                                                                         \
+            hipLaunchKernelGGL((blocks_f64_staged_kernel<double2, NTV>), dim3(blocks), dim3(kStagedThreads), 0, s, \
+                               (const double2 *)L.Su, (const double2 *)L.Sd, L.desc, L.V, L.chunk_sites,         \
+                               L.n_chunks, L.K, (int)work, (double2 *)L.partial);                                \
+        else                                                                                                      \
+            hipLaunchKernelGGL((blocks_f64_staged_kernel<float2, NTV>), dim3(blocks), dim3(kStagedThreads), 0, s,  \
+                               (const float2 *)L.Su, (const float2 *)L.Sd, L.desc, L.V, L.chunk_sites,           \
+                               L.n_chunks, L.K, (int)work, (double2 *)L.partial);                                \
+        break;
+            WICK_STAGED(1) WICK_STAGED(2) WICK_STAGED(3) WICK_STAGED(4)
+#undef WICK_STAGED
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        const int64_t waves = (int64_t)n_units * L.n_chunks * n_ct;
+        const int wpb = 4;
+        const int64_t blocks = round8((waves + wpb - 1) / wpb);
+        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+        if (L.dtype == 0)
+            hipLaunchKernelGGL(blocks_f64_kernel<double2>, dim3((unsigned)blocks), dim3(64 * wpb), 0, s,
+                               (const double2 *)L.Su, (const double2 *)L.Sd, L.groups, n_units, L.V, L.chunk_sites,
+                               L.n_chunks, L.K, waves, (double2 *)L.partial);
+        else
+            hipLaunchKernelGGL(blocks_f64_kernel<float2>, dim3((unsigned)blocks), dim3(64 * wpb), 0, s,
+                               (const float2 *)L.Su, (const float2 *)L.Sd, L.groups, n_units, L.V, L.chunk_sites,
+                               L.n_chunks, L.K, waves, (double2 *)L.partial);
+    }
     pr.stop();
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

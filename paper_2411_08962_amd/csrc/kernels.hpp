@@ -21,12 +21,30 @@ struct EGroupDev {
 
 constexpr int kNTiles = 9;  // 144 (i2, i3) columns = 9 MFMA tiles of 16
 
+// All groups of a plan for the staged block kernel. Its workgroup has one
+// wave per column tile; every wave accumulates every m-tile ("tile") of the
+// groups of one pass. Groups are packed into passes of at most kPassTiles
+// tiles (the accumulators of a pass stay in registers).
+constexpr int kMaxGroupsStaged = 8;
+constexpr int kMaxPasses = 8;
+constexpr int kPassTiles = 4;
+struct BlocksDesc {
+    int32_t n_groups, n_passes;
+    int32_t pass_tiles[kMaxPasses];
+    int32_t pass_ngroups[kMaxPasses], pass_groups[kMaxPasses][kPassTiles];
+    int32_t tile_group[kMaxPasses][kPassTiles], tile_mt[kMaxPasses][kPassTiles];  // group -1: unused
+    EGroupDev groups[kMaxGroupsStaged];
+};
+
 struct BlockLaunch {
     const void *Su, *Sd;
     int dtype;               // 0 = complex128, 1 = complex64
     int prec;                // wick_precision
     const EGroupDev *groups; // device
     int n_groups;
+    const BlocksDesc *desc;  // device; null when the plan exceeds the staged kernel's limits
+    int n_tiles;             // most tiles in one pass (staged kernel)
+    int n_passes;
     int64_t V;
     int T, n_cfg, K;
     int chunk_sites, n_chunks;

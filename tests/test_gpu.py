@@ -73,6 +73,16 @@ def test_blocks_deuteron_4x4x4x8():
     check_blocks(ops.deuteron(), B, hu, hd, range(8))
 
 
+def test_blocks_generic_kernel(monkeypatch):
+    # the one-wave-per-tile kernel that serves plans beyond the staged kernel's limits
+    monkeypatch.setenv("WICK_BLOCKS_KERNEL", "generic")
+    w = W()
+    pl = w.plan_std("3He")
+    hu, hd, du, dd = props(8, 1, (3, 3, 3, 2))
+    B = w.blocks(pl, du, dd).cpu().numpy()
+    check_blocks(ops.helium3(), B, hu, hd, range(2))
+
+
 def test_blocks_ragged_volume_and_c64():
     # V = 30 is not a multiple of the 4 sites per MFMA step nor of a chunk
     w = W()
