@@ -75,6 +75,8 @@ wick_status workspace(hipStream_t s, size_t bytes, void **out)
 struct DevPlan {
     int device = -1;
     int n_tiles = 0, n_passes = 0;
+    NucDesc *nuc = nullptr;  // null unless every kind has nucleon form
+    int nuc_tiles = 0, nuc_passes = 0;
     EGroupDev *groups = nullptr;
     BlocksDesc *desc = nullptr;  // null when the staged kernel does not apply
     uint16_t *kidx = nullptr;
@@ -179,6 +181,58 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
         if ((e = hipMemcpy(d.desc, &bd, sizeof(bd), hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(e, "plan upload hipMemcpy");
     }
+    // the nucleon kernel's descriptor, packed into passes the same way
+    if (!p->nucgroups.empty() && p->nucgroups.size() <= (size_t)kMaxGroupsStaged) {
+        NucDesc nd;
+        std::memset(&nd, 0, sizeof(nd));
+        for (int pp = 0; pp < kMaxPasses; ++pp)
+            for (int t = 0; t < kPassTiles; ++t) nd.tile_group[pp][t] = -1;
+        bool ok = true;
+        int maxt = 0;
+        const int G = (int)p->nucgroups.size();
+        std::vector<int> order(G);
+        for (int g = 0; g < G; ++g) order[g] = g;
+        auto tiles_of = [&](int g) { return (12 * (int)p->nucgroups[g].kinds.size() + 15) / 16; };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tiles_of(x) > tiles_of(y); });
+        nd.n_groups = G;
+        for (int g : order) {
+            const NucGroup &ng = p->nucgroups[g];
+            NucGroupDev &h = nd.groups[g];
+            h.f = ng.f;
+            h.g = ng.g;
+            h.npair = (int)ng.pairs.size();
+            h.nk = (int)ng.kinds.size();
+            for (int i = 0; i < h.npair; ++i) {
+                h.s2[i] = ng.pairs[i][0];
+                h.s3[i] = ng.pairs[i][1];
+                h.m[i] = ng.pairs[i][2];
+            }
+            for (int k = 0; k < h.nk; ++k) {
+                h.alpha[k] = ng.alpha[k];
+                h.kind_out[k] = ng.kinds[k];
+            }
+            const int mt = tiles_of(g);
+            int pp = 0;
+            while (pp < nd.n_passes && nd.pass_tiles[pp] + mt > kPassTiles) ++pp;
+            if (mt > kPassTiles || pp == kMaxPasses) { ok = false; break; }
+            if (pp == nd.n_passes) ++nd.n_passes;
+            nd.pass_groups[pp][nd.pass_ngroups[pp]++] = g;
+            for (int t = 0; t < mt; ++t) {
+                nd.tile_group[pp][nd.pass_tiles[pp]] = g;
+                nd.tile_mt[pp][nd.pass_tiles[pp]] = t;
+                ++nd.pass_tiles[pp];
+            }
+            maxt = std::max(maxt, nd.pass_tiles[pp]);
+        }
+        if (ok) {
+            if ((e = hipMalloc(&d.nuc, sizeof(NucDesc))) != hipSuccess)
+                return fail(WICK_ENOMEM, std::string("plan upload hipMalloc: ") + hipGetErrorString(e));
+            if ((e = hipMemcpy(d.nuc, &nd, sizeof(nd), hipMemcpyHostToDevice)) != hipSuccess)
+                return hip_fail(e, "plan upload hipMemcpy");
+            d.nuc_tiles = maxt;
+            d.nuc_passes = nd.n_passes;
+        }
+    }
     size_t nt = (size_t)p->n_terms;
     size_t coef_n = p->coef_real ? nt : 2 * nt;
     if ((e = hipMalloc(&d.groups, std::max<size_t>(1, hg.size()) * sizeof(EGroupDev))) != hipSuccess ||
@@ -271,9 +325,16 @@ wick_status do_blocks(wick_plan_s *p, const void *Su, const void *Sd, int dtype,
     L.desc = dp->desc;
     L.n_tiles = dp->n_tiles;
     L.n_passes = dp->n_passes;
-    // WICK_BLOCKS_KERNEL=generic selects the one-wave-per-tile kernel (tests use it)
-    if (const char *k = std::getenv("WICK_BLOCKS_KERNEL"))
-        if (std::strcmp(k, "generic") == 0) L.desc = nullptr;
+    L.nuc = dp->nuc;
+    L.nuc_tiles = dp->nuc_tiles;
+    L.nuc_passes = dp->nuc_passes;
+    // WICK_BLOCKS_KERNEL selects a kernel for testing: "generic" (one wave per
+    // tile, global loads) or "rows" (staged, general E rows); default: nucleon
+    // form when every kind has it, else rows, else generic.
+    if (const char *k = std::getenv("WICK_BLOCKS_KERNEL")) {
+        if (std::strcmp(k, "generic") == 0) { L.desc = nullptr; L.nuc = nullptr; }
+        if (std::strcmp(k, "rows") == 0) L.nuc = nullptr;
+    }
     L.V = V;
     L.T = dims[3];
     L.n_cfg = n_cfg;
@@ -382,6 +443,7 @@ void release_device_tables(wick_plan_s *p)
         (void)hipDeviceSynchronize();
         (void)hipFree(d.groups);
         (void)hipFree(d.desc);
+        (void)hipFree(d.nuc);
         (void)hipFree(d.kidx);
         (void)hipFree(d.coef);
     }

@@ -46,6 +46,15 @@ struct EGroup {
     std::vector<std::array<int8_t, 2>> aop;
 };
 
+// Kinds of nucleon form (Eqs. 2.2-2.3 and the projected forms of Sec. 3.3):
+//   w_k(j1, j2, j3) = delta(spin j1 = alpha_k) eps[c(j1), c(j3), c(j2)] M[s(j3)][s(j2)]
+// with one integer diquark matrix M shared by the group's kinds.
+struct NucGroup {
+    int f = 0, g = 1;
+    std::vector<std::array<int8_t, 3>> pairs;  // (s2, s3, M[s3][s2]) for the nonzero entries of M
+    std::vector<int> kinds, alpha;             // block-kind indices and their sink spins
+};
+
 struct DeviceTable {
     int device = -1;
     void *kidx = nullptr;   // uint16 [A][n_terms]
@@ -60,6 +69,7 @@ struct wick_plan_s {
     int A = 0;
     std::vector<wick::KindDef> kinds;   // block kinds (used by sink patterns)
     std::vector<wick::EGroup> egroups;
+    std::vector<wick::NucGroup> nucgroups;  // empty unless every block kind has nucleon form
     int64_t n_terms = 0;
     std::vector<uint16_t> kidx;         // [A][n_terms]
     std::vector<double> coef_re, coef_im;
@@ -79,7 +89,7 @@ wick_status fail(wick_status st, const std::string &msg);
 
 // planner (plan.cpp)
 wick_status build_plan(const wick_nucleus_desc *d, wick_plan_t *out);
-void factor_kinds(wick_plan_s *p);  // fills p->egroups
+void factor_kinds(wick_plan_s *p);  // fills p->egroups and p->nucgroups
 wick_status save_plan(const wick_plan_s *p, const char *path);
 wick_status load_plan(const char *path, wick_plan_t *out);
 

@@ -288,6 +288,134 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_f64_staged_kernel(
     }
 }
 
+// Nucleon-form kernel: the staged layout (9 waves, one column tile each,
+// double-buffered LDS propagators) with the E rows computed as colour cross
+// products per nonzero diquark-matrix entry (6 LDS loads for all three rows)
+// and Aop read with a per-lane base offset fixed at kernel start.
+template <typename TIn, int NT>
+__global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_f64_kernel(
+    const TIn *__restrict__ Su, const TIn *__restrict__ Sd, const NucDesc *__restrict__ desc, int64_t V,
+    int chunk_sites, int n_chunks, int K, int n_work, double2 *__restrict__ partial)
+{
+    __shared__ double2 sbuf[2][kSB][2][144];
+    const int lb = xcd_block();
+    if (lb >= n_work) return;
+    const int pass = lb % desc->n_passes;
+    const int chunk = (lb / desc->n_passes) % n_chunks;
+    const int64_t ct = lb / desc->n_passes / n_chunks;
+    const int nt = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const int n = nt * 16 + c, i2 = n / 12, i3 = n % 12;
+    const int npg = desc->pass_ngroups[pass];
+    const int32_t *tgroup = desc->tile_group[pass];
+
+    // per tile: offset of this lane's Aop column inside a site's S_f (row 3*alpha, column i1);
+    // padded columns (kind index past the group) read a valid entry and are never stored
+    int bo[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int g = tgroup[t];
+        bo[t] = 0;
+        if (g >= 0) {
+            const NucGroupDev &G = desc->groups[g];
+            const int m = desc->tile_mt[pass][t] * 16 + c;
+            const int kk = m / 12 < G.nk ? m / 12 : G.nk - 1;
+            bo[t] = 36 * G.alpha[kk] + m % 12;
+        }
+    }
+    d4 acc[NT][2];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t][0] = acc[t][1] = d4{0, 0, 0, 0};
+
+    const int64_t x0 = (int64_t)chunk * chunk_sites;
+    const int64_t x1 = x0 + chunk_sites < V ? x0 + chunk_sites : V;
+    const int nb = (int)((x1 - x0 + kSB - 1) / kSB);
+    const TIn *base[2] = {Su + ct * V * 144, Sd + ct * V * 144};
+    constexpr int kPer = kSB * 2 * 144 / kStagedThreads;
+    double2 stage[kPer];
+    auto load = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = threadIdx.x + u * kStagedThreads;     // [site][flavor][144]
+            const int s = e / 288, fl = (e / 144) & 1, j = e % 144;
+            const int64_t x = x0 + (int64_t)b * kSB + s;
+            if (x < x1) {
+                const TIn v = base[fl][x * 144 + j];
+                stage[u] = double2{(double)v.x, (double)v.y};
+            } else {
+                stage[u] = double2{0.0, 0.0};
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) (&sbuf[buf][0][0][0])[threadIdx.x + u * kStagedThreads] = stage[u];
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int b = 0; b < nb; ++b) {
+        const int cur = b & 1;
+        if (b + 1 < nb) load(b + 1);
+        for (int st = 0; st < kSB / 4; ++st) {
+            const int s = st * 4 + q;   // sites past the end are zeros in LDS: E = 0
+            for (int gl = 0; gl < npg; ++gl) {
+                const int g = desc->pass_groups[pass][gl];
+                const NucGroupDev &G = desc->groups[g];
+                const double2 *sfb = sbuf[cur][s][G.f];
+                const double2 *sgb = sbuf[cur][s][G.g];
+                double e0x = 0, e0y = 0, e1x = 0, e1y = 0, e2x = 0, e2y = 0;
+                for (int p = 0; p < G.npair; ++p) {
+                    const double2 *pa = sgb + 36 * G.s2[p] + i2;
+                    const double2 *pb = sfb + 36 * G.s3[p] + i3;
+                    const double2 a0 = pa[0], a1 = pa[12], a2 = pa[24];
+                    const double2 b0 = pb[0], b1 = pb[12], b2 = pb[24];
+                    const double m = (double)G.m[p];
+                    // E_r = M * sum eps[r][c3][c2] a_c2 b_c3
+                    e0x += m * ((a2.x * b1.x - a2.y * b1.y) - (a1.x * b2.x - a1.y * b2.y));
+                    e0y += m * ((a2.x * b1.y + a2.y * b1.x) - (a1.x * b2.y + a1.y * b2.x));
+                    e1x += m * ((a0.x * b2.x - a0.y * b2.y) - (a2.x * b0.x - a2.y * b0.y));
+                    e1y += m * ((a0.x * b2.y + a0.y * b2.x) - (a2.x * b0.y + a2.y * b0.x));
+                    e2x += m * ((a1.x * b0.x - a1.y * b0.y) - (a0.x * b1.x - a0.y * b1.y));
+                    e2y += m * ((a1.x * b0.y + a1.y * b0.x) - (a0.x * b1.y + a0.y * b1.x));
+                }
+                const double ex[3] = {e0x, e1x, e2x}, ey[3] = {e0y, e1y, e2y};
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    double2 v[NT];
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        if (tgroup[t] != g) continue;
+                        v[t] = sfb[bo[t] + 12 * r];
+                        acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex[r], v[t].x, acc[t][0], 0, 0, 0);
+                        acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex[r], v[t].y, acc[t][1], 0, 0, 0);
+                    }
+                    const double ney = -ey[r];
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        if (tgroup[t] != g) continue;
+                        acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ney, v[t].y, acc[t][0], 0, 0, 0);
+                        acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey[r], v[t].x, acc[t][1], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        if (b + 1 < nb) store(cur ^ 1);
+        __syncthreads();
+    }
+    double2 *P = partial + (ct * n_chunks + chunk) * (int64_t)K * 1728;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (tgroup[t] < 0) continue;
+        const NucGroupDev &G = desc->groups[tgroup[t]];
+        const int m = desc->tile_mt[pass][t] * 16 + c, kk = m / 12, i1 = m % 12;
+        if (kk >= G.nk) continue;
+        double2 *row = P + ((int64_t)G.kind_out[kk] * 12 + i1) * 144 + nt * 16 + q;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) row[4 * v] = double2{acc[t][0][v], acc[t][1][v]};
+    }
+}
+
 // Sum the chunks in order and antisymmetrise: B[c] = sum_ch P[i1][i2,i3] - P[i3][i2,i1].
 __global__ __launch_bounds__(256) void blocks_reduce_kernel(const double2 *__restrict__ partial, int n_chunks,
                                                             int K, int64_t n_out, double2 *__restrict__ B)
@@ -394,7 +522,27 @@ hipError_t launch_blocks(const BlockLaunch &L, hipStream_t s)
     const int n_units = L.n_groups * kNTiles;
     const int64_t n_ct = (int64_t)L.n_cfg * L.T;
     Probe pr("blocks", s);
-    if (L.desc) {
+    if (L.nuc) {
+        const int64_t work = n_ct * L.n_chunks * L.nuc_passes;
+        if (work > 0x7ffffff0LL) return hipErrorInvalidValue;
+        const unsigned blocks = (unsigned)round8(work);
+        switch (L.nuc_tiles) {
+#define WICK_NUC(NTV)                                                                                              \
+    case NTV:                                                                                                      \
+        if (L.dtype == 0)                                                                                          \
+            hipLaunchKernelGGL((blocks_nucleon_f64_kernel<double2, NTV>), dim3(blocks), dim3(kStagedThreads), 0, s, \
+                               (const double2 *)L.Su, (const double2 *)L.Sd, L.nuc, L.V, L.chunk_sites,           \
+                               L.n_chunks, L.K, (int)work, (double2 *)L.partial);                                 \
+        else                                                                                                       \
+            hipLaunchKernelGGL((blocks_nucleon_f64_kernel<float2, NTV>), dim3(blocks), dim3(kStagedThreads), 0, s,  \
+                               (const float2 *)L.Su, (const float2 *)L.Sd, L.nuc, L.V, L.chunk_sites,             \
+                               L.n_chunks, L.K, (int)work, (double2 *)L.partial);                                 \
+        break;
+            WICK_NUC(1) WICK_NUC(2) WICK_NUC(3) WICK_NUC(4)
+#undef WICK_NUC
+        default: return hipErrorInvalidValue;
+        }
+    } else if (L.desc) {
         const int64_t work = n_ct * L.n_chunks * L.n_passes;
         if (work > 0x7ffffff0LL) return hipErrorInvalidValue;
         const unsigned blocks = (unsigned)round8(work);

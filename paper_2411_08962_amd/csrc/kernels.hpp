@@ -36,6 +36,22 @@ struct BlocksDesc {
     EGroupDev groups[kMaxGroupsStaged];
 };
 
+// Nucleon-form groups (see NucGroup): E_r(x)[i2,i3] = sum over the nonzero
+// M[s3][s2] of M * (colour cross product of S_g(x)[3 s2 + ., i2] and
+// S_f(x)[3 s3 + ., i3])_r, and Aop_k(x, r)[i1] = S_f(x)[3 alpha_k + r, i1].
+struct NucGroupDev {
+    int32_t f, g, npair, nk;
+    int8_t s2[16], s3[16], m[16];
+    int32_t alpha[kMaxKindsPerGroup], kind_out[kMaxKindsPerGroup];
+};
+struct NucDesc {
+    int32_t n_groups, n_passes;
+    int32_t pass_ngroups[kMaxPasses], pass_groups[kMaxPasses][kPassTiles];
+    int32_t pass_tiles[kMaxPasses];
+    int32_t tile_group[kMaxPasses][kPassTiles], tile_mt[kMaxPasses][kPassTiles];  // group -1: unused
+    NucGroupDev groups[kMaxGroupsStaged];
+};
+
 struct BlockLaunch {
     const void *Su, *Sd;
     int dtype;               // 0 = complex128, 1 = complex64
@@ -45,6 +61,8 @@ struct BlockLaunch {
     const BlocksDesc *desc;  // device; null when the plan exceeds the staged kernel's limits
     int n_tiles;             // most tiles in one pass (staged kernel)
     int n_passes;
+    const NucDesc *nuc;      // device; set when every kind has nucleon form
+    int nuc_tiles, nuc_passes;
     int64_t V;
     int T, n_cfg, K;
     int chunk_sites, n_chunks;

@@ -612,9 +612,71 @@ wick_status build_plan(const wick_nucleus_desc *d, wick_plan_t *out)
 // Rows of a kind: w(j1, ., .) for each j1 with nonzero weights. Rows equal up
 // to sign (across kinds of one flavor pattern) are computed once per site and
 // shared (they are the diquark rows eps * (C g5 P) of the nucleon operators).
+namespace {
+int eps3(int a, int b, int c)
+{
+    if (a == b || b == c || a == c) return 0;
+    return ((a > b) + (a > c) + (b > c)) & 1 ? -1 : 1;
+}
+
+// Exact test of the nucleon form; on success alpha and M (row s3, column s2).
+bool nucleon_form(const KindDef &kd, int &alpha, int M[4][4])
+{
+    if (kd.w.empty()) return false;
+    int W[12][12][12] = {};
+    for (size_t n = 0; n < kd.w.size(); ++n) {
+        if (kd.w[n].im != 0 || std::llabs(kd.w[n].re) > 127) return false;
+        W[kd.j[n][0]][kd.j[n][1]][kd.j[n][2]] += (int)kd.w[n].re;
+    }
+    alpha = kd.j[0][0] / 3;
+    // read M off the (c1, c2, c3) = (0, 2, 1) entries, where eps[0][1][2] = +1
+    for (int s3 = 0; s3 < 4; ++s3)
+        for (int s2 = 0; s2 < 4; ++s2) M[s3][s2] = W[3 * alpha][3 * s2 + 2][3 * s3 + 1];
+    for (int j1 = 0; j1 < 12; ++j1)
+        for (int j2 = 0; j2 < 12; ++j2)
+            for (int j3 = 0; j3 < 12; ++j3) {
+                int want = j1 / 3 == alpha ? eps3(j1 % 3, j3 % 3, j2 % 3) * M[j3 / 3][j2 / 3] : 0;
+                if (W[j1][j2][j3] != want) return false;
+            }
+    return true;
+}
+}  // namespace
+
 void factor_kinds(wick_plan_s *p)
 {
     p->egroups.clear();
+    p->nucgroups.clear();
+    {
+        // nucleon groups: kinds of one flavor pattern sharing M, at most kMaxKindsPerGroup each
+        std::vector<NucGroup> ng;
+        std::vector<std::array<int, 16>> keys;
+        bool all = true;
+        for (int k = 0; k < (int)p->kinds.size() && all; ++k) {
+            int alpha, M[4][4];
+            if (!nucleon_form(p->kinds[k], alpha, M)) { all = false; break; }
+            std::array<int, 16> key;
+            for (int i = 0; i < 16; ++i) key[i] = M[i / 4][i % 4];
+            int gi = -1;
+            for (size_t g = 0; g < ng.size(); ++g)
+                if (keys[g] == key && ng[g].f == p->kinds[k].flav[0] && ng[g].g == p->kinds[k].flav[1] &&
+                    (int)ng[g].kinds.size() < kMaxKindsPerGroup)
+                    gi = (int)g;
+            if (gi < 0) {
+                NucGroup g;
+                g.f = p->kinds[k].flav[0];
+                g.g = p->kinds[k].flav[1];
+                for (int s3 = 0; s3 < 4; ++s3)
+                    for (int s2 = 0; s2 < 4; ++s2)
+                        if (M[s3][s2]) g.pairs.push_back({(int8_t)s2, (int8_t)s3, (int8_t)M[s3][s2]});
+                ng.push_back(g);
+                keys.push_back(key);
+                gi = (int)ng.size() - 1;
+            }
+            ng[gi].kinds.push_back(k);
+            ng[gi].alpha.push_back(alpha);
+        }
+        if (all) p->nucgroups = ng;
+    }
     const int K = (int)p->kinds.size();
     using Row = std::vector<std::pair<int, int64_t>>;  // (j2*12+j3, w)
     struct KR { int j1; Row row; int sign; };

@@ -73,9 +73,10 @@ def test_blocks_deuteron_4x4x4x8():
     check_blocks(ops.deuteron(), B, hu, hd, range(8))
 
 
-def test_blocks_generic_kernel(monkeypatch):
-    # the one-wave-per-tile kernel that serves plans beyond the staged kernel's limits
-    monkeypatch.setenv("WICK_BLOCKS_KERNEL", "generic")
+@pytest.mark.parametrize("kernel", ["generic", "rows"])
+def test_blocks_fallback_kernels(monkeypatch, kernel):
+    # the kernels that serve plans without nucleon-form kinds
+    monkeypatch.setenv("WICK_BLOCKS_KERNEL", kernel)
     w = W()
     pl = w.plan_std("3He")
     hu, hd, du, dd = props(8, 1, (3, 3, 3, 2))
