@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <deque>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
@@ -75,8 +76,10 @@ wick_status workspace(hipStream_t s, size_t bytes, void **out)
 struct DevPlan {
     int device = -1;
     int n_tiles = 0, n_passes = 0;
-    NucDesc *nuc = nullptr;  // null unless every kind has nucleon form
+    NucDesc *nuc = nullptr;  // null unless every kind has nucleon form (FP64 packing)
     int nuc_tiles = 0, nuc_passes = 0;
+    NucDesc *nuc_split = nullptr;  // the same for the split-precision modes
+    int split_tiles = 0, split_passes = 0;
     EGroupDev *groups = nullptr;
     BlocksDesc *desc = nullptr;  // null when the staged kernel does not apply
     uint16_t *kidx = nullptr;
@@ -84,7 +87,7 @@ struct DevPlan {
 };
 
 std::mutex g_dev_mu;
-std::map<const wick_plan_s *, std::vector<DevPlan>> g_dev;
+std::map<const wick_plan_s *, std::deque<DevPlan>> g_dev;  // deque: stable element addresses
 
 wick_status check_groups(const wick_plan_s *p)
 {
@@ -181,56 +184,60 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
         if ((e = hipMemcpy(d.desc, &bd, sizeof(bd), hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(e, "plan upload hipMemcpy");
     }
-    // the nucleon kernel's descriptor, packed into passes the same way
+    // the nucleon kernel's descriptors: groups packed into passes of at most
+    // 4 m-tiles (FP64) or 3 (split modes, which also hold FP32 accumulators)
     if (!p->nucgroups.empty() && p->nucgroups.size() <= (size_t)kMaxGroupsStaged) {
-        NucDesc nd;
-        std::memset(&nd, 0, sizeof(nd));
-        for (int pp = 0; pp < kMaxPasses; ++pp)
-            for (int t = 0; t < kPassTiles; ++t) nd.tile_group[pp][t] = -1;
-        bool ok = true;
-        int maxt = 0;
-        const int G = (int)p->nucgroups.size();
-        std::vector<int> order(G);
-        for (int g = 0; g < G; ++g) order[g] = g;
-        auto tiles_of = [&](int g) { return (12 * (int)p->nucgroups[g].kinds.size() + 15) / 16; };
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tiles_of(x) > tiles_of(y); });
-        nd.n_groups = G;
-        for (int g : order) {
-            const NucGroup &ng = p->nucgroups[g];
-            NucGroupDev &h = nd.groups[g];
-            h.f = ng.f;
-            h.g = ng.g;
-            h.npair = (int)ng.pairs.size();
-            h.nk = (int)ng.kinds.size();
-            for (int i = 0; i < h.npair; ++i) {
-                h.s2[i] = ng.pairs[i][0];
-                h.s3[i] = ng.pairs[i][1];
-                h.m[i] = ng.pairs[i][2];
+        for (int which = 0; which < 2; ++which) {
+            const int cap = which == 0 ? 4 : 3;
+            NucDesc nd;
+            std::memset(&nd, 0, sizeof(nd));
+            for (int pp = 0; pp < kMaxPasses; ++pp)
+                for (int t = 0; t < kPassTiles; ++t) nd.tile_group[pp][t] = -1;
+            bool ok = true;
+            int maxt = 0;
+            const int G = (int)p->nucgroups.size();
+            std::vector<int> order(G);
+            for (int g = 0; g < G; ++g) order[g] = g;
+            auto tiles_of = [&](int g) { return (12 * (int)p->nucgroups[g].kinds.size() + 15) / 16; };
+            std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tiles_of(x) > tiles_of(y); });
+            nd.n_groups = G;
+            for (int g : order) {
+                const NucGroup &ng = p->nucgroups[g];
+                NucGroupDev &h = nd.groups[g];
+                h.f = ng.f;
+                h.g = ng.g;
+                h.npair = (int)ng.pairs.size();
+                h.nk = (int)ng.kinds.size();
+                for (int i = 0; i < h.npair; ++i) {
+                    h.s2[i] = ng.pairs[i][0];
+                    h.s3[i] = ng.pairs[i][1];
+                    h.m[i] = ng.pairs[i][2];
+                }
+                for (int k = 0; k < h.nk; ++k) {
+                    h.alpha[k] = ng.alpha[k];
+                    h.kind_out[k] = ng.kinds[k];
+                }
+                const int mt = tiles_of(g);
+                int pp = 0;
+                while (pp < nd.n_passes && nd.pass_tiles[pp] + mt > cap) ++pp;
+                if (mt > cap || pp == kMaxPasses) { ok = false; break; }
+                if (pp == nd.n_passes) ++nd.n_passes;
+                nd.pass_groups[pp][nd.pass_ngroups[pp]++] = g;
+                for (int t = 0; t < mt; ++t) {
+                    nd.tile_group[pp][nd.pass_tiles[pp]] = g;
+                    nd.tile_mt[pp][nd.pass_tiles[pp]] = t;
+                    ++nd.pass_tiles[pp];
+                }
+                maxt = std::max(maxt, nd.pass_tiles[pp]);
             }
-            for (int k = 0; k < h.nk; ++k) {
-                h.alpha[k] = ng.alpha[k];
-                h.kind_out[k] = ng.kinds[k];
-            }
-            const int mt = tiles_of(g);
-            int pp = 0;
-            while (pp < nd.n_passes && nd.pass_tiles[pp] + mt > kPassTiles) ++pp;
-            if (mt > kPassTiles || pp == kMaxPasses) { ok = false; break; }
-            if (pp == nd.n_passes) ++nd.n_passes;
-            nd.pass_groups[pp][nd.pass_ngroups[pp]++] = g;
-            for (int t = 0; t < mt; ++t) {
-                nd.tile_group[pp][nd.pass_tiles[pp]] = g;
-                nd.tile_mt[pp][nd.pass_tiles[pp]] = t;
-                ++nd.pass_tiles[pp];
-            }
-            maxt = std::max(maxt, nd.pass_tiles[pp]);
-        }
-        if (ok) {
-            if ((e = hipMalloc(&d.nuc, sizeof(NucDesc))) != hipSuccess)
+            if (!ok) continue;
+            NucDesc **dst = which == 0 ? &d.nuc : &d.nuc_split;
+            if ((e = hipMalloc(dst, sizeof(NucDesc))) != hipSuccess)
                 return fail(WICK_ENOMEM, std::string("plan upload hipMalloc: ") + hipGetErrorString(e));
-            if ((e = hipMemcpy(d.nuc, &nd, sizeof(nd), hipMemcpyHostToDevice)) != hipSuccess)
+            if ((e = hipMemcpy(*dst, &nd, sizeof(nd), hipMemcpyHostToDevice)) != hipSuccess)
                 return hip_fail(e, "plan upload hipMemcpy");
-            d.nuc_tiles = maxt;
-            d.nuc_passes = nd.n_passes;
+            (which == 0 ? d.nuc_tiles : d.split_tiles) = maxt;
+            (which == 0 ? d.nuc_passes : d.split_passes) = nd.n_passes;
         }
     }
     size_t nt = (size_t)p->n_terms;
@@ -261,7 +268,8 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
 // ------------------------------------------------------------- tuning
 struct Tune {
     int chunk_sites = 256;
-    int64_t slice_len = 0;  // 0: derived
+    int64_t slice_len = 0;      // 0: derived
+    int batch_chunk_sites = 0;  // 0: derived
 };
 std::mutex g_tune_mu;
 std::map<std::string, Tune> g_tune;
@@ -311,7 +319,7 @@ wick_status do_blocks(wick_plan_s *p, const void *Su, const void *Sd, int dtype,
     if (st != WICK_OK) return st;
     if (!Su || !Sd || !B) return fail(WICK_EINVAL, "wick_blocks: null pointer");
     if (dtype != WICK_C128 && dtype != WICK_C64) return fail(WICK_EINVAL, "wick_blocks: bad dtype");
-    if (prec != WICK_P64) return fail(WICK_EUNSUPPORTED, "wick_blocks: only WICK_P64 is available in this build");
+    if (prec < WICK_P64 || prec > WICK_PB6) return fail(WICK_EINVAL, "wick_blocks: bad precision");
     DevPlan *dp;
     if ((st = device_plan(p, s, &dp)) != WICK_OK) return st;
     Tune tu = tune_for(p, dims, dtype, prec);
@@ -325,9 +333,9 @@ wick_status do_blocks(wick_plan_s *p, const void *Su, const void *Sd, int dtype,
     L.desc = dp->desc;
     L.n_tiles = dp->n_tiles;
     L.n_passes = dp->n_passes;
-    L.nuc = dp->nuc;
-    L.nuc_tiles = dp->nuc_tiles;
-    L.nuc_passes = dp->nuc_passes;
+    L.nuc = prec == WICK_P64 ? dp->nuc : dp->nuc_split;
+    L.nuc_tiles = prec == WICK_P64 ? dp->nuc_tiles : dp->split_tiles;
+    L.nuc_passes = prec == WICK_P64 ? dp->nuc_passes : dp->split_passes;
     // WICK_BLOCKS_KERNEL selects a kernel for testing: "generic" (one wave per
     // tile, global loads) or "rows" (staged, general E rows); default: nucleon
     // form when every kind has it, else rows, else generic.
@@ -335,6 +343,8 @@ wick_status do_blocks(wick_plan_s *p, const void *Su, const void *Sd, int dtype,
         if (std::strcmp(k, "generic") == 0) { L.desc = nullptr; L.nuc = nullptr; }
         if (std::strcmp(k, "rows") == 0) L.nuc = nullptr;
     }
+    if (prec != WICK_P64 && !L.nuc)
+        return fail(WICK_EUNSUPPORTED, "wick_blocks: split precision needs kinds of nucleon form");
     L.V = V;
     L.T = dims[3];
     L.n_cfg = n_cfg;
@@ -412,12 +422,163 @@ void prof_flush_locked()
     g_prof_pending.clear();
 }
 
+
+// ---------------------------------------------------------------- batches
+// A batch of (plan, configuration) items runs as one launch of each kernel
+// (blocks, block reduction, term sum, finalize) over device work lists. The
+// lists, workspaces and (optionally) a hipGraph of the launches are cached per
+// (plans, items, shapes, pointers, stream).
+struct BatchEntry {
+    int device = -1;
+    std::vector<const wick_plan_s *> plans;
+    BatchBlockItem *bitems = nullptr;
+    BatchBlockWork *bwork = nullptr;
+    int64_t *bout = nullptr;
+    BatchContractItem *citems = nullptr;
+    BatchContractWork *cwork = nullptr;
+    void *partial = nullptr, *B = nullptr, *cpartial = nullptr;
+    BatchLaunch L{};
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+std::mutex g_batch_mu;
+std::map<std::string, BatchEntry> g_batch;
+thread_local bool t_capturing = false;
+
+void free_batch(BatchEntry &b)
+{
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(b.device);
+    (void)hipDeviceSynchronize();
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    if (b.cap) (void)hipStreamDestroy(b.cap);
+    for (void *q : {(void *)b.bitems, (void *)b.bwork, (void *)b.bout, (void *)b.citems, (void *)b.cwork, b.partial,
+                    b.B, b.cpartial})
+        if (q) (void)hipFree(q);
+    (void)hipSetDevice(cur);
+}
+
+template <class T> wick_status upload(const std::vector<T> &h, T **d)
+{
+    hipError_t e = hipMalloc((void **)d, std::max<size_t>(1, h.size()) * sizeof(T));
+    if (e != hipSuccess) return fail(WICK_ENOMEM, std::string("batch hipMalloc: ") + hipGetErrorString(e));
+    if (!h.empty() && (e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "batch hipMemcpy");
+    return WICK_OK;
+}
+
+wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_items, const void *S_u,
+                        const void *S_d, int dtype, const int32_t dims[4], int64_t V, int prec, int chunk_hint,
+                        double *C, BatchEntry &b)
+{
+    const int T = dims[3];
+    (void)hipGetDevice(&b.device);
+    std::vector<BatchBlockItem> bi(n_items);
+    std::vector<BatchBlockWork> bw;
+    std::vector<int64_t> bout(n_items + 1, 0);
+    std::vector<BatchContractItem> ci(n_items);
+    std::vector<BatchContractWork> cw;
+    int nt_max = 0, max_K = 0, passes_max = 1;
+    std::vector<DevPlan *> dps(n_items);
+    for (int i = 0; i < n_items; ++i) {
+        wick_plan_s *p = plans[items[i].plan];
+        wick_status st = device_plan(p, nullptr, &dps[i]);
+        if (st != WICK_OK) return st;
+        DevPlan *dp = dps[i];
+        const NucDesc *nd = prec == WICK_P64 ? dp->nuc : dp->nuc_split;
+        if (!nd) return fail(WICK_EUNSUPPORTED, "batched path needs kinds of nucleon form");
+        nt_max = std::max(nt_max, prec == WICK_P64 ? dp->nuc_tiles : dp->split_tiles);
+        passes_max = std::max(passes_max, prec == WICK_P64 ? dp->nuc_passes : dp->split_passes);
+        max_K = std::max(max_K, (int)p->kinds.size());
+    }
+    // sites per chunk: enough workgroups to fill the chip, at least 64 sites each
+    int64_t want_chunks = std::max<int64_t>(1, (2048 + (int64_t)n_items * T * passes_max - 1) /
+                                                   ((int64_t)n_items * T * passes_max));
+    int chunk_sites = chunk_hint > 0 ? chunk_hint
+                                     : (int)std::max<int64_t>(64, (V + want_chunks - 1) / want_chunks);
+    chunk_sites = (chunk_sites + 7) / 8 * 8;
+    const int n_chunks = (int)((V + chunk_sites - 1) / chunk_sites);
+    int64_t part = 0, bo = 0, cpart = 0;
+    const int64_t want_slices = std::max<int64_t>(1, (4096 + (int64_t)n_items * T - 1) / ((int64_t)n_items * T));
+    for (int i = 0; i < n_items; ++i) {
+        wick_plan_s *p = plans[items[i].plan];
+        DevPlan *dp = dps[i];
+        const int K = (int)p->kinds.size();
+        const int passes = prec == WICK_P64 ? dp->nuc_passes : dp->split_passes;
+        bi[i].desc = prec == WICK_P64 ? dp->nuc : dp->nuc_split;
+        bi[i].s_off = (int64_t)items[i].cfg * T * V * 144;
+        bi[i].part_off = part;
+        bi[i].b_off = bo;
+        bi[i].K = K;
+        bi[i].n_chunks = n_chunks;
+        part += (int64_t)T * n_chunks * K * 1728;
+        bout[i] = bo;
+        bo += (int64_t)T * K * 792;
+        for (int t = 0; t < T; ++t)
+            for (int ch = 0; ch < n_chunks; ++ch)
+                for (int ps = 0; ps < passes; ++ps) bw.push_back({i, t, ch, ps});
+        BatchContractItem &c = ci[i];
+        c.kidx = dp->kidx;
+        c.coef = dp->coef;
+        c.N = p->n_terms;
+        c.slice_len = std::max<int64_t>(2048, (c.N + want_slices - 1) / want_slices);
+        c.n_slices = (int)std::max<int64_t>(1, (c.N + c.slice_len - 1) / c.slice_len);
+        c.b_off = bi[i].b_off;
+        c.part_off = cpart;
+        c.A = p->A;
+        c.K = K;
+        c.coef_real = p->coef_real ? 1 : 0;
+        cpart += (int64_t)T * c.n_slices;
+        for (int t = 0; t < T; ++t)
+            for (int sl = 0; sl < c.n_slices; ++sl) cw.push_back({i, t, sl, 0});
+    }
+    bout[n_items] = bo;
+    if (bw.size() > 0x7ffffff0ULL || cw.size() > 0x7ffffff0ULL) return fail(WICK_ETOOBIG, "batch too large");
+    wick_status st;
+    if ((st = upload(bi, &b.bitems)) != WICK_OK || (st = upload(bw, &b.bwork)) != WICK_OK ||
+        (st = upload(bout, &b.bout)) != WICK_OK || (st = upload(ci, &b.citems)) != WICK_OK ||
+        (st = upload(cw, &b.cwork)) != WICK_OK)
+        return st;
+    hipError_t e;
+    if ((e = hipMalloc(&b.partial, std::max<int64_t>(1, part) * 16)) != hipSuccess ||
+        (e = hipMalloc(&b.B, std::max<int64_t>(1, bo) * 16)) != hipSuccess ||
+        (e = hipMalloc(&b.cpartial, std::max<int64_t>(1, cpart) * 16)) != hipSuccess)
+        return fail(WICK_ENOMEM, std::string("batch workspace hipMalloc: ") + hipGetErrorString(e));
+    BatchLaunch &L = b.L;
+    L.Su = S_u;
+    L.Sd = S_d;
+    L.dtype = dtype;
+    L.prec = prec;
+    L.nt_max = nt_max;
+    L.V = V;
+    L.T = T;
+    L.chunk_sites = chunk_sites;
+    L.n_items = n_items;
+    L.bitems = b.bitems;
+    L.bwork = b.bwork;
+    L.n_bwork = (int)bw.size();
+    L.bout_off = b.bout;
+    L.n_bout = bo;
+    L.citems = b.citems;
+    L.cwork = b.cwork;
+    L.n_cwork = (int)cw.size();
+    L.max_K = max_K;
+    L.partial = (double *)b.partial;
+    L.B = (double *)b.B;
+    L.cpartial = (double *)b.cpartial;
+    L.C = C;
+    if (contract_lds_bytes(max_K) > 160 * 1024 - 256) return fail(WICK_EUNSUPPORTED, "batch: more than 12 kinds");
+    return WICK_OK;
+}
 }  // namespace
 
 Probe::Probe(const char *n, hipStream_t st) : name(n), s(st)
 {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof_on) return;
+    if (!g_prof_on || t_capturing) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
     (void)hipEventRecord(a, s);
 }
@@ -444,6 +605,7 @@ void release_device_tables(wick_plan_s *p)
         (void)hipFree(d.groups);
         (void)hipFree(d.desc);
         (void)hipFree(d.nuc);
+        (void)hipFree(d.nuc_split);
         (void)hipFree(d.kidx);
         (void)hipFree(d.coef);
     }
@@ -521,6 +683,17 @@ wick_status wick_plan_load(const char *path, wick_plan_t *out) { WICK_TRY(return
 void wick_plan_destroy(wick_plan_t p)
 {
     if (!p) return;
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        for (auto it = g_batch.begin(); it != g_batch.end();) {
+            if (std::find(it->second.plans.begin(), it->second.plans.end(), p) != it->second.plans.end()) {
+                free_batch(it->second);
+                it = g_batch.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
     release_device_tables(p);
     delete p;
 }
@@ -542,38 +715,61 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
                             const void *S_u, const void *S_d, wick_dtype dtype, const int32_t dims[4], int32_t n_cfg,
                             wick_precision prec, int32_t use_graph, wick_stream_t stream, double *C)
 {
-    if (!plans || n_plans < 1 || !items || n_items < 1 || !C)
-        return fail(WICK_EINVAL, "wick_correlator: bad plans / items / output");
+    if (!plans || n_plans < 1 || !items || n_items < 1 || !C || !S_u || !S_d)
+        return fail(WICK_EINVAL, "wick_correlator: bad plans / items / pointers");
     int64_t V;
     wick_status st = check_dims(dims, n_cfg, &V);
     if (st != WICK_OK) return st;
+    if (dtype != WICK_C128 && dtype != WICK_C64) return fail(WICK_EINVAL, "wick_correlator: bad dtype");
+    if (prec < WICK_P64 || prec > WICK_PB6) return fail(WICK_EINVAL, "wick_correlator: bad precision");
     for (int i = 0; i < n_plans; ++i)
         if (!plans[i]) return fail(WICK_EINVAL, "wick_correlator: null plan");
     for (int i = 0; i < n_items; ++i)
         if (items[i].plan < 0 || items[i].plan >= n_plans || items[i].cfg < 0 || items[i].cfg >= n_cfg)
             return fail(WICK_EINVAL, "wick_correlator: item index out of range");
-    (void)use_graph;
     hipStream_t s = (hipStream_t)stream;
-    const int T = dims[3];
-    const size_t esz = dtype == WICK_C128 ? 16 : 8;
-    const size_t cfg_bytes = (size_t)T * V * 144 * esz;
-    // blocks of one configuration for the largest plan, then its contraction
-    size_t maxK = 0;
-    for (int i = 0; i < n_plans; ++i) maxK = std::max(maxK, plans[i]->kinds.size());
-    double *Bbuf = nullptr;
-    hipError_t e = hipMalloc(&Bbuf, std::max<size_t>(1, (size_t)T * maxK * 792 * 16));
-    if (e != hipSuccess) return fail(WICK_ENOMEM, "wick_correlator: block buffer");
-    for (int i = 0; i < n_items && st == WICK_OK; ++i) {
-        wick_plan_s *p = plans[items[i].plan];
-        const char *su = (const char *)S_u + items[i].cfg * cfg_bytes;
-        const char *sd = (const char *)S_d + items[i].cfg * cfg_bytes;
-        WICK_TRY(st = do_blocks(p, su, sd, (int)dtype, dims, 1, (int)prec, s, Bbuf));
-        if (st != WICK_OK) break;
-        WICK_TRY(st = do_contract(p, Bbuf, 1, T, s, C + (size_t)i * T * 2, nullptr));
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::ostringstream key;
+    key << dev << ':' << (const void *)s << ':' << S_u << ':' << S_d << ':' << (const void *)C << ':' << dims[0] << 'x'
+        << dims[1] << 'x' << dims[2] << 'x' << dims[3] << ':' << n_cfg << ':' << (int)dtype << ':' << (int)prec << ':'
+        << (use_graph ? 1 : 0);
+    for (int i = 0; i < n_plans; ++i) key << ':' << (const void *)plans[i];
+    for (int i = 0; i < n_items; ++i) key << ';' << items[i].plan << ',' << items[i].cfg;
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    auto it = g_batch.find(key.str());
+    if (it == g_batch.end()) {
+        BatchEntry b;
+        const Tune tu = tune_for(plans[0], dims, (int)dtype, (int)prec);
+        WICK_TRY(st = build_batch(plans, items, n_items, S_u, S_d, (int)dtype, dims, V, (int)prec,
+                                  tu.batch_chunk_sites, C, b));
+        if (st != WICK_OK) {
+            free_batch(b);
+            return st;
+        }
+        for (int i = 0; i < n_plans; ++i) b.plans.push_back(plans[i]);
+        if (use_graph) {
+            hipError_t e;
+            if ((e = hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking)) != hipSuccess ||
+                (e = hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+                free_batch(b);
+                return hip_fail(e, "wick_correlator: graph capture");
+            }
+            t_capturing = true;
+            hipError_t le = launch_batch(b.L, b.cap);
+            t_capturing = false;
+            e = hipStreamEndCapture(b.cap, &b.graph);
+            if (le != hipSuccess || e != hipSuccess ||
+                (e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0)) != hipSuccess) {
+                free_batch(b);
+                return hip_fail(le != hipSuccess ? le : e, "wick_correlator: graph capture");
+            }
+        }
+        it = g_batch.emplace(key.str(), b).first;
     }
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(Bbuf);
-    return st;
+    hipError_t e = it->second.exec ? hipGraphLaunch(it->second.exec, s) : launch_batch(it->second.L, s);
+    if (e != hipSuccess) return hip_fail(e, "wick_correlator launch");
+    return WICK_OK;
 }
 
 wick_status wick_autotune(wick_plan_t p, const int32_t dims[4], wick_dtype dtype, wick_precision prec,
@@ -586,6 +782,11 @@ wick_status wick_autotune(wick_plan_t p, const int32_t dims[4], wick_dtype dtype
 
 wick_status wick_shutdown(void)
 {
+    {
+        std::lock_guard<std::mutex> lb(g_batch_mu);
+        for (auto &kv : g_batch) free_batch(kv.second);
+        g_batch.clear();
+    }
     std::lock_guard<std::mutex> lk(g_ws_mu);
     int cur = 0;
     (void)hipGetDevice(&cur);

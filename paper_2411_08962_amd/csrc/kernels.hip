@@ -289,20 +289,77 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_f64_staged_kernel(
 }
 
 // Nucleon-form kernel: the staged layout (9 waves, one column tile each,
-// double-buffered LDS propagators) with the E rows computed as colour cross
-// products per nonzero diquark-matrix entry (6 LDS loads for all three rows)
-// and Aop read with a per-lane base offset fixed at kernel start.
-template <typename TIn, int NT>
-__global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_f64_kernel(
-    const TIn *__restrict__ Su, const TIn *__restrict__ Sd, const NucDesc *__restrict__ desc, int64_t V,
-    int chunk_sites, int n_chunks, int K, int n_work, double2 *__restrict__ partial)
+// double-buffered LDS propagators in FP64) with the E rows computed in FP64
+// as colour cross products per nonzero diquark-matrix entry (6 LDS loads for
+// all three rows) and Aop read with a per-lane base offset fixed at kernel
+// start. The GEMM runs, by MODE, on
+//   P64: v_mfma_f64_16x16x4f64 (four real MFMAs per complex product);
+//   P32: v_mfma_f32_16x16x4f32 with E and Aop rounded to FP32;
+//   PB3: v_mfma_f32_16x16x32_bf16, E and Aop split into two BF16 limbs
+//        (hi + lo), the three products hi*hi + hi*lo + lo*hi packed along K:
+//        one MFMA per real/imaginary output;
+//   PB6: three limbs (hi + mid + lo) and the six products of limb order <= 2:
+//        two MFMAs per output.
+// In the split modes the operands are scaled by exact powers of two (2^-2e
+// for E, 2^-e for Aop, e the exponent of the largest propagator entry of the
+// chunk's first batch), the MFMAs accumulate in FP32 for one batch of kSB
+// sites only, and each batch is folded into FP64 accumulators with the exact
+// factor 2^3e. Operand layout of the BF16 MFMA (measured): A[i][k] at lane
+// i + 16*(k/8), element k%8; B[k][j] at lane j + 16*(k/8); D as for the f32
+// 16x16x4 MFMA, row 4*(lane/16) + item, column lane%16. Lane group q
+// (= k/8 for BF16, = k for the 16x16x4 MFMAs) is site q of the step.
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split2(double x, __bf16 &h, __bf16 &l)
 {
+    h = (__bf16)(float)x;
+    l = (__bf16)(float)(x - (double)(float)h);
+}
+__device__ __forceinline__ void split3(double x, __bf16 &h, __bf16 &m, __bf16 &l)
+{
+    h = (__bf16)(float)x;
+    const double r = x - (double)(float)h;
+    m = (__bf16)(float)r;
+    l = (__bf16)(float)(r - (double)(float)m);
+}
+
+template <typename TIn, int NT, int MODE>
+__global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_kernel(
+    const TIn *__restrict__ Su, const TIn *__restrict__ Sd, const NucDesc *__restrict__ desc_one, int64_t V,
+    int chunk_sites, int n_chunks_one, int K_one, int n_work, double2 *__restrict__ partial,
+    const BatchBlockItem *__restrict__ bitems, const BatchBlockWork *__restrict__ bwork, int T)
+{
+    constexpr bool kSplit = MODE != WICK_P64;
     __shared__ double2 sbuf[2][kSB][2][144];
+    __shared__ double smax[kNTiles];
     const int lb = xcd_block();
     if (lb >= n_work) return;
-    const int pass = lb % desc->n_passes;
-    const int chunk = (lb / desc->n_passes) % n_chunks;
-    const int64_t ct = lb / desc->n_passes / n_chunks;
+    // one plan: the workgroup's (cfg*T + t, chunk, pass) follow from its id;
+    // a batch: from its work entry and its item's descriptor
+    const NucDesc *desc;
+    int pass, chunk, n_chunks, K;
+    int64_t s_off, p_off;
+    if (bwork) {
+        const BatchBlockWork w = bwork[lb];
+        const BatchBlockItem &it = bitems[w.item];
+        desc = it.desc;
+        pass = w.pass;
+        chunk = w.chunk;
+        n_chunks = it.n_chunks;
+        K = it.K;
+        s_off = it.s_off + (int64_t)w.t * V * 144;
+        p_off = it.part_off + ((int64_t)w.t * n_chunks + chunk) * K * 1728;
+    } else {
+        desc = desc_one;
+        n_chunks = n_chunks_one;
+        K = K_one;
+        pass = lb % desc->n_passes;
+        chunk = (lb / desc->n_passes) % n_chunks;
+        const int64_t ct = lb / desc->n_passes / n_chunks;
+        s_off = ct * V * 144;
+        p_off = (ct * n_chunks + chunk) * (int64_t)K * 1728;
+    }
     const int nt = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
     const int n = nt * 16 + c, i2 = n / 12, i3 = n % 12;
@@ -330,7 +387,7 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_f64_kernel(
     const int64_t x0 = (int64_t)chunk * chunk_sites;
     const int64_t x1 = x0 + chunk_sites < V ? x0 + chunk_sites : V;
     const int nb = (int)((x1 - x0 + kSB - 1) / kSB);
-    const TIn *base[2] = {Su + ct * V * 144, Sd + ct * V * 144};
+    const TIn *base[2] = {Su + s_off, Sd + s_off};
     constexpr int kPer = kSB * 2 * 144 / kStagedThreads;
     double2 stage[kPer];
     auto load = [&](int b) {
@@ -352,13 +409,38 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_f64_kernel(
         for (int u = 0; u < kPer; ++u) (&sbuf[buf][0][0][0])[threadIdx.x + u * kStagedThreads] = stage[u];
     };
     load(0);
+    // split modes: operand scales 2^-2e (E) and 2^-e (Aop), from the first batch
+    double scE = 1.0, scA = 1.0, unscale = 1.0;
+    if constexpr (kSplit) {
+        double mx = 0.0;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) mx = fmax(mx, fmax(fabs(stage[u].x), fabs(stage[u].y)));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+        if (lane == 0) smax[nt] = mx;
+        __syncthreads();
+        mx = 0.0;
+#pragma unroll
+        for (int w = 0; w < kNTiles; ++w) mx = fmax(mx, smax[w]);
+        const int e = mx > 0.0 ? ilogb(mx) : 0;
+        scA = ldexp(1.0, -e);
+        scE = ldexp(1.0, -2 * e);
+        unscale = ldexp(1.0, 3 * e);
+    }
     store(0);
     __syncthreads();
     for (int b = 0; b < nb; ++b) {
         const int cur = b & 1;
         if (b + 1 < nb) load(b + 1);
+        f4 acc32[NT][2];
+        if constexpr (kSplit) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc32[t][0] = acc32[t][1] = f4{0, 0, 0, 0};
+        }
+#pragma unroll 1
         for (int st = 0; st < kSB / 4; ++st) {
             const int s = st * 4 + q;   // sites past the end are zeros in LDS: E = 0
+#pragma unroll 1
             for (int gl = 0; gl < npg; ++gl) {
                 const int g = desc->pass_groups[pass][gl];
                 const NucGroupDev &G = desc->groups[g];
@@ -379,40 +461,114 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_f64_kernel(
                     e2x += m * ((a1.x * b0.x - a1.y * b0.y) - (a0.x * b1.x - a0.y * b1.y));
                     e2y += m * ((a1.x * b0.y + a1.y * b0.x) - (a0.x * b1.y + a0.y * b1.x));
                 }
-                const double ex[3] = {e0x, e1x, e2x}, ey[3] = {e0y, e1y, e2y};
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
-                    double2 v[NT];
+                    const double ex = r == 0 ? e0x : (r == 1 ? e1x : e2x);
+                    const double ey = r == 0 ? e0y : (r == 1 ? e1y : e2y);
+                    if constexpr (MODE == WICK_P64) {
+                        double2 v[NT];
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        if (tgroup[t] != g) continue;
-                        v[t] = sfb[bo[t] + 12 * r];
-                        acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex[r], v[t].x, acc[t][0], 0, 0, 0);
-                        acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex[r], v[t].y, acc[t][1], 0, 0, 0);
-                    }
-                    const double ney = -ey[r];
+                        for (int t = 0; t < NT; ++t) {
+                            if (tgroup[t] != g) continue;
+                            v[t] = sfb[bo[t] + 12 * r];
+                            acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, v[t].x, acc[t][0], 0, 0, 0);
+                            acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, v[t].y, acc[t][1], 0, 0, 0);
+                        }
+                        const double ney = -ey;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        if (tgroup[t] != g) continue;
-                        acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ney, v[t].y, acc[t][0], 0, 0, 0);
-                        acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey[r], v[t].x, acc[t][1], 0, 0, 0);
+                        for (int t = 0; t < NT; ++t) {
+                            if (tgroup[t] != g) continue;
+                            acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ney, v[t].y, acc[t][0], 0, 0, 0);
+                            acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey, v[t].x, acc[t][1], 0, 0, 0);
+                        }
+                    } else if constexpr (MODE == WICK_P32) {
+                        const float fx = (float)(ex * scE), fy = (float)(ey * scE);
+                        float2 v[NT];
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) {
+                            if (tgroup[t] != g) continue;
+                            const double2 d = sfb[bo[t] + 12 * r];
+                            v[t] = float2{(float)(d.x * scA), (float)(d.y * scA)};
+                            acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fx, v[t].x, acc32[t][0], 0, 0, 0);
+                            acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fx, v[t].y, acc32[t][1], 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) {
+                            if (tgroup[t] != g) continue;
+                            acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(-fy, v[t].y, acc32[t][0], 0, 0, 0);
+                            acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fy, v[t].x, acc32[t][1], 0, 0, 0);
+                        }
+                    } else if constexpr (MODE == WICK_PB3) {
+                        __bf16 xh, xl, yh, yl;
+                        split2(ex * scE, xh, xl);
+                        split2(ey * scE, yh, yl);
+                        const __bf16 z = (__bf16)0.0f;
+                        const bf8 Aop = bf8{xh, xh, xl, yh, yh, yl, z, z};
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) {
+                            if (tgroup[t] != g) continue;
+                            const double2 d = sfb[bo[t] + 12 * r];
+                            __bf16 axh, axl, ayh, ayl;
+                            split2(d.x * scA, axh, axl);
+                            split2(d.y * scA, ayh, ayl);
+                            const bf8 Bre = bf8{axh, axl, axh, -ayh, -ayl, -ayh, z, z};
+                            const bf8 Bim = bf8{ayh, ayl, ayh, axh, axl, axh, z, z};
+                            acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop, Bre, acc32[t][0], 0, 0, 0);
+                            acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop, Bim, acc32[t][1], 0, 0, 0);
+                        }
+                    } else {
+                        __bf16 xh, xm, xl, yh, ym, yl;
+                        split3(ex * scE, xh, xm, xl);
+                        split3(ey * scE, yh, ym, yl);
+                        const __bf16 z = (__bf16)0.0f;
+                        const bf8 Ax = bf8{xh, xh, xm, xh, xm, xl, z, z};
+                        const bf8 Ay = bf8{yh, yh, ym, yh, ym, yl, z, z};
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) {
+                            if (tgroup[t] != g) continue;
+                            const double2 d = sfb[bo[t] + 12 * r];
+                            __bf16 ah, am, al, bh, bm, bl;
+                            split3(d.x * scA, ah, am, al);
+                            split3(d.y * scA, bh, bm, bl);
+                            const bf8 Bx = bf8{ah, am, ah, al, am, ah, z, z};
+                            const bf8 By = bf8{bh, bm, bh, bl, bm, bh, z, z};
+                            const bf8 nBy = bf8{-bh, -bm, -bh, -bl, -bm, -bh, z, z};
+                            acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ax, Bx, acc32[t][0], 0, 0, 0);
+                            acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ax, By, acc32[t][1], 0, 0, 0);
+                            acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ay, nBy, acc32[t][0], 0, 0, 0);
+                            acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ay, Bx, acc32[t][1], 0, 0, 0);
+                        }
                     }
                 }
             }
         }
+        if constexpr (kSplit) {
+            // fold this batch's FP32 sums into the FP64 accumulators (exact rescale)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    acc[t][0][v] += (double)acc32[t][0][v] * unscale;
+                    acc[t][1][v] += (double)acc32[t][1][v] * unscale;
+                }
+        }
         if (b + 1 < nb) store(cur ^ 1);
         __syncthreads();
     }
-    double2 *P = partial + (ct * n_chunks + chunk) * (int64_t)K * 1728;
+    double2 *P = partial + p_off;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         if (tgroup[t] < 0) continue;
         const NucGroupDev &G = desc->groups[tgroup[t]];
         const int m = desc->tile_mt[pass][t] * 16 + c, kk = m / 12, i1 = m % 12;
         if (kk >= G.nk) continue;
-        double2 *row = P + ((int64_t)G.kind_out[kk] * 12 + i1) * 144 + nt * 16 + q;
+        double2 *row = P + ((int64_t)G.kind_out[kk] * 12 + i1) * 144 + nt * 16;
+        // f64 MFMA result: row 4*v + q; f32 / bf16 MFMA result: row 4*q + v
 #pragma unroll
-        for (int v = 0; v < 4; ++v) row[4 * v] = double2{acc[t][0][v], acc[t][1][v]};
+        for (int v = 0; v < 4; ++v) {
+            const int rr = kSplit ? 4 * q + v : 4 * v + q;
+            row[rr] = double2{acc[t][0][v], acc[t][1][v]};
+        }
     }
 }
 
@@ -513,6 +669,118 @@ __global__ void contract_finalize_kernel(const double2 *__restrict__ partial, in
     C[ct] = double2{sr, si};
 }
 
+
+// ------------------------------------------------------------------ batches
+// Reduction of a batch's partial blocks: one thread per output entry of all
+// items; the item of an entry is found by binary search in the prefix table.
+__global__ __launch_bounds__(256) void batch_reduce_kernel(const double2 *__restrict__ partial,
+                                                           const BatchBlockItem *__restrict__ items,
+                                                           const int64_t *__restrict__ out_off, int n_items,
+                                                           int T, int64_t n_out, double2 *__restrict__ B)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_out) return;
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (out_off[mid] <= idx) lo = mid; else hi = mid - 1;
+    }
+    const BatchBlockItem &it = items[lo];
+    const int64_t r = idx - out_off[lo];
+    const int per = it.K * 792;
+    const int t = (int)(r / per);
+    const int e = (int)(r % per);
+    const int kind = e / 792, cc = e % 792, pr = cc / 12, i2 = cc % 12;
+    int i3 = 1;
+    while ((i3 + 1) * i3 / 2 <= pr) ++i3;
+    const int i1 = pr - i3 * (i3 - 1) / 2;
+    const double2 *P = partial + it.part_off + (int64_t)t * it.n_chunks * it.K * 1728 + (int64_t)kind * 1728;
+    const int oa = i1 * 144 + i2 * 12 + i3, ob = i3 * 144 + i2 * 12 + i1;
+    double sx = 0.0, sy = 0.0;
+    for (int ch = 0; ch < it.n_chunks; ++ch) {
+        const double2 a = P[(int64_t)ch * it.K * 1728 + oa];
+        const double2 b = P[(int64_t)ch * it.K * 1728 + ob];
+        sx += a.x - b.x;
+        sy += a.y - b.y;
+    }
+    B[idx] = double2{sx, sy};
+}
+
+// Term sum of a batch: one workgroup per (item, t, slice) work entry; A, the
+// number of kinds and the coefficient type are read from the item.
+__global__ __launch_bounds__(256) void contract_batch_kernel(const double2 *__restrict__ B,
+                                                             const BatchContractItem *__restrict__ items,
+                                                             const BatchContractWork *__restrict__ work, int n_work,
+                                                             double2 *__restrict__ partial)
+{
+    extern __shared__ double2 sB[];
+    __shared__ double red[2][4];
+    const int lb = xcd_block();
+    if (lb >= n_work) return;
+    const BatchContractWork w = work[lb];
+    const BatchContractItem &it = items[w.item];
+    const int A = it.A, K = it.K;
+    const double2 *Bc = B + it.b_off + (int64_t)w.t * K * 792;
+    for (int i = threadIdx.x; i < K * 792; i += blockDim.x) sB[i] = Bc[i];
+    __syncthreads();
+    const int64_t N = it.N;
+    const int64_t n0 = (int64_t)w.slice * it.slice_len;
+    const int64_t n1 = n0 + it.slice_len < N ? n0 + it.slice_len : N;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+        double2 p = sB[it.kidx[n]];
+        for (int a = 1; a < A; ++a) {
+            const double2 b = sB[it.kidx[(int64_t)a * N + n]];
+            p = double2{p.x * b.x - p.y * b.y, p.x * b.y + p.y * b.x};
+        }
+        if (it.coef_real) {
+            const double cr = it.coef[n];
+            ar += cr * p.x;
+            ai += cr * p.y;
+        } else {
+            const double cr = it.coef[2 * n], ci = it.coef[2 * n + 1];
+            ar += cr * p.x - ci * p.y;
+            ai += cr * p.y + ci * p.x;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        ar += __shfl_xor(ar, off);
+        ai += __shfl_xor(ai, off);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wv] = ar;
+        red[1][wv] = ai;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sr = 0.0, si = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            sr += red[0][i];
+            si += red[1][i];
+        }
+        partial[it.part_off + (int64_t)w.t * it.n_slices + w.slice] = double2{sr, si};
+    }
+}
+
+__global__ void batch_finalize_kernel(const double2 *__restrict__ partial,
+                                      const BatchContractItem *__restrict__ items, int n_items, int T,
+                                      double2 *__restrict__ C)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_items * T) return;
+    const int i = idx / T, t = idx % T;
+    const BatchContractItem &it = items[i];
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < it.n_slices; ++s) {
+        const double2 v = partial[it.part_off + (int64_t)t * it.n_slices + s];
+        sr += v.x;
+        si += v.y;
+    }
+    C[idx] = double2{sr, si};
+}
+
 int round8(int64_t n) { return (int)((n + 7) / 8 * 8); }
 
 }  // namespace
@@ -526,22 +794,25 @@ hipError_t launch_blocks(const BlockLaunch &L, hipStream_t s)
         const int64_t work = n_ct * L.n_chunks * L.nuc_passes;
         if (work > 0x7ffffff0LL) return hipErrorInvalidValue;
         const unsigned blocks = (unsigned)round8(work);
-        switch (L.nuc_tiles) {
-#define WICK_NUC(NTV)                                                                                              \
-    case NTV:                                                                                                      \
-        if (L.dtype == 0)                                                                                          \
-            hipLaunchKernelGGL((blocks_nucleon_f64_kernel<double2, NTV>), dim3(blocks), dim3(kStagedThreads), 0, s, \
-                               (const double2 *)L.Su, (const double2 *)L.Sd, L.nuc, L.V, L.chunk_sites,           \
-                               L.n_chunks, L.K, (int)work, (double2 *)L.partial);                                 \
-        else                                                                                                       \
-            hipLaunchKernelGGL((blocks_nucleon_f64_kernel<float2, NTV>), dim3(blocks), dim3(kStagedThreads), 0, s,  \
-                               (const float2 *)L.Su, (const float2 *)L.Sd, L.nuc, L.V, L.chunk_sites,             \
-                               L.n_chunks, L.K, (int)work, (double2 *)L.partial);                                 \
-        break;
-            WICK_NUC(1) WICK_NUC(2) WICK_NUC(3) WICK_NUC(4)
+        bool done = false;
+#define WICK_NUC(NTV, MODE)                                                                                       \
+    if (L.nuc_tiles == NTV && L.prec == MODE) {                                                                   \
+        if (L.dtype == 0)                                                                                         \
+            hipLaunchKernelGGL((blocks_nucleon_kernel<double2, NTV, MODE>), dim3(blocks), dim3(kStagedThreads), 0, \
+                               s, (const double2 *)L.Su, (const double2 *)L.Sd, L.nuc, L.V, L.chunk_sites,         \
+                               L.n_chunks, L.K, (int)work, (double2 *)L.partial, nullptr, nullptr, L.T);         \
+        else                                                                                                      \
+            hipLaunchKernelGGL((blocks_nucleon_kernel<float2, NTV, MODE>), dim3(blocks), dim3(kStagedThreads), 0,  \
+                               s, (const float2 *)L.Su, (const float2 *)L.Sd, L.nuc, L.V, L.chunk_sites,           \
+                               L.n_chunks, L.K, (int)work, (double2 *)L.partial, nullptr, nullptr, L.T);         \
+        done = true;                                                                                              \
+    }
+        WICK_NUC(1, WICK_P64) WICK_NUC(2, WICK_P64) WICK_NUC(3, WICK_P64) WICK_NUC(4, WICK_P64)
+        WICK_NUC(1, WICK_P32) WICK_NUC(2, WICK_P32) WICK_NUC(3, WICK_P32)
+        WICK_NUC(1, WICK_PB3) WICK_NUC(2, WICK_PB3) WICK_NUC(3, WICK_PB3)
+        WICK_NUC(1, WICK_PB6) WICK_NUC(2, WICK_PB6) WICK_NUC(3, WICK_PB6)
 #undef WICK_NUC
-        default: return hipErrorInvalidValue;
-        }
+        if (!done) return hipErrorInvalidValue;
     } else if (L.desc) {
         const int64_t work = n_ct * L.n_chunks * L.n_passes;
         if (work > 0x7ffffff0LL) return hipErrorInvalidValue;
@@ -633,6 +904,64 @@ hipError_t launch_contract(const ContractLaunch &L, hipStream_t s)
     hipLaunchKernelGGL(contract_finalize_kernel, dim3((L.n_ct + 255) / 256), dim3(256), 0, s,
                        (const double2 *)L.partial, L.n_ct, L.n_slices, (double2 *)L.C);
     pr2.stop();
+    return hipGetLastError();
+}
+
+
+hipError_t launch_batch(const BatchLaunch &L, hipStream_t s)
+{
+    {
+        Probe pr("blocks", s);
+        const unsigned blocks = (unsigned)round8(L.n_bwork);
+        bool done = false;
+#define WICK_BNUC(NTV, MODE)                                                                                      \
+    if (L.nt_max == NTV && L.prec == MODE) {                                                                      \
+        if (L.dtype == 0)                                                                                         \
+            hipLaunchKernelGGL((blocks_nucleon_kernel<double2, NTV, MODE>), dim3(blocks), dim3(kStagedThreads), 0, \
+                               s, (const double2 *)L.Su, (const double2 *)L.Sd, nullptr, L.V, L.chunk_sites, 0, 0, \
+                               L.n_bwork, (double2 *)L.partial, L.bitems, L.bwork, L.T);                         \
+        else                                                                                                      \
+            hipLaunchKernelGGL((blocks_nucleon_kernel<float2, NTV, MODE>), dim3(blocks), dim3(kStagedThreads), 0,  \
+                               s, (const float2 *)L.Su, (const float2 *)L.Sd, nullptr, L.V, L.chunk_sites, 0, 0,   \
+                               L.n_bwork, (double2 *)L.partial, L.bitems, L.bwork, L.T);                         \
+        done = true;                                                                                              \
+    }
+        WICK_BNUC(1, WICK_P64) WICK_BNUC(2, WICK_P64) WICK_BNUC(3, WICK_P64) WICK_BNUC(4, WICK_P64)
+        WICK_BNUC(1, WICK_P32) WICK_BNUC(2, WICK_P32) WICK_BNUC(3, WICK_P32)
+        WICK_BNUC(1, WICK_PB3) WICK_BNUC(2, WICK_PB3) WICK_BNUC(3, WICK_PB3)
+        WICK_BNUC(1, WICK_PB6) WICK_BNUC(2, WICK_PB6) WICK_BNUC(3, WICK_PB6)
+#undef WICK_BNUC
+        if (!done) return hipErrorInvalidValue;
+        pr.stop();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    {
+        Probe pr("blocks_reduce", s);
+        hipLaunchKernelGGL(batch_reduce_kernel, dim3((unsigned)((L.n_bout + 255) / 256)), dim3(256), 0, s,
+                           (const double2 *)L.partial, L.bitems, L.bout_off, L.n_items, L.T, L.n_bout, (double2 *)L.B);
+        pr.stop();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    {
+        Probe pr("contract", s);
+        const size_t lds = contract_lds_bytes(L.max_K);
+        if (lds > 160 * 1024 - 256) return hipErrorInvalidValue;
+        static const hipError_t attr = hipFuncSetAttribute((const void *)contract_batch_kernel,
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                           160 * 1024 - 256);
+        (void)attr;
+        hipLaunchKernelGGL(contract_batch_kernel, dim3((unsigned)round8(L.n_cwork)), dim3(256), lds, s,
+                           (const double2 *)L.B, L.citems, L.cwork, L.n_cwork, (double2 *)L.cpartial);
+        pr.stop();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    Probe pr("contract_finalize", s);
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3((L.n_items * L.T + 255) / 256), dim3(256), 0, s,
+                       (const double2 *)L.cpartial, L.citems, L.n_items, L.T, (double2 *)L.C);
+    pr.stop();
     return hipGetLastError();
 }
 

@@ -52,6 +52,29 @@ struct NucDesc {
     NucGroupDev groups[kMaxGroupsStaged];
 };
 
+// Batched launches: one work entry per workgroup and one descriptor per
+// (nucleus, configuration) item, so one launch covers items of different
+// nuclei (different A, kinds and tables).
+struct BatchBlockItem {
+    const NucDesc *desc;   // the item's plan (split or FP64 packing)
+    int64_t s_off;         // offset of the item's configuration in S_u / S_d (entries)
+    int64_t part_off;      // offset of the item's partial blocks (double2 entries)
+    int64_t b_off;         // offset of the item's blocks in B (double2 entries)
+    int32_t K, n_chunks;
+};
+struct BatchBlockWork {
+    int32_t item, t, chunk, pass;
+};
+struct BatchContractItem {
+    const uint16_t *kidx;
+    const double *coef;
+    int64_t N, slice_len, b_off, part_off;  // part_off: first partial of (item, t = 0)
+    int32_t A, K, coef_real, n_slices;
+};
+struct BatchContractWork {
+    int32_t item, t, slice, pad;
+};
+
 struct BlockLaunch {
     const void *Su, *Sd;
     int dtype;               // 0 = complex128, 1 = complex64
@@ -71,6 +94,27 @@ struct BlockLaunch {
 };
 
 hipError_t launch_blocks(const BlockLaunch &L, hipStream_t s);
+
+struct BatchLaunch {
+    const void *Su, *Sd;
+    int dtype, prec, nt_max;
+    int64_t V;
+    int T, chunk_sites;
+    int n_items;
+    const BatchBlockItem *bitems;     // device
+    const BatchBlockWork *bwork;      // device
+    int n_bwork;
+    const int64_t *bout_off;          // device [n_items + 1]: prefix of T*K*792
+    int64_t n_bout;
+    const BatchContractItem *citems;  // device
+    const BatchContractWork *cwork;   // device
+    int n_cwork, max_K;
+    double *partial;                  // workspace: raw partial blocks of every item
+    double *B;                        // blocks of every item
+    double *cpartial;                 // contraction partials
+    double *C;                        // [n_items][T][2]
+};
+hipError_t launch_batch(const BatchLaunch &L, hipStream_t s);
 
 struct ContractLaunch {
     const double *B;         // [n_ct][K][792][2]

@@ -180,6 +180,33 @@ def test_correlator_entry_point_mixed_nuclei():
     check_C(ops.helium3(), plans[1], C[1:2], hu[0:1], hd[0:1], range(2))
 
 
+@pytest.mark.parametrize("prec", ["p64", "pb6"])
+def test_batched_graph_replays_match_eager(prec):
+    """One batch of uneven-A items (2H, 3He, 3H on five configurations), run
+    eagerly and as a captured hipGraph replayed three times, with eager work and
+    synchronisations between the replays; every replay must equal the eager
+    result bitwise, and the eager result must match the oracle."""
+    torch = _torch()
+    w = W()
+    plans = [w.plan_std("2H"), w.plan_std("3He"), w.plan_std("3H")]
+    items = [(0, 0), (1, 1), (2, 2), (0, 3), (1, 4), (2, 0)]
+    hu, hd, du, dd = props(12, 5, (3, 2, 2, 3))
+    eager = w.correlator(plans, items, du, dd, prec).cpu().numpy()
+    names = ["2H", "3He", "3H"]
+    for i, (pi, cfg) in enumerate(items):
+        check_C(ops.by_name(names[pi]), plans[pi], eager[i:i + 1], hu[cfg:cfg + 1], hd[cfg:cfg + 1], range(3),
+                tol=TOL64 if prec == "p64" else SPLIT_TOL[prec])
+    out = torch.zeros((len(items), 3, 2), dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        out.zero_()
+        junk = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        w.correlator(plans, items, du, dd, prec, use_graph=True, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), rep
+        del junk
+
+
 # -------------------------------------------------- full-size workload, sampled
 def test_helium3_16cubed_x32_sampled():
     """The benchmark workload (3He on 16^3 x 32, complex128, FP64), at its full
@@ -193,3 +220,44 @@ def test_helium3_16cubed_x32_sampled():
     Bn = B.cpu().numpy()
     check_blocks(ops.helium3(), Bn, hu, hd, [31])
     check_C(ops.helium3(), pl, C, hu, hd, [0, 31])
+
+
+# ------------------------------------------------------------ split precision
+# The bound of the split paths is |dC| <= 1e-8 * sum|terms| for FP32 operands
+# (P32) and three BF16 limbs (PB6). Two BF16 limbs (PB3) carry ~2^-16 relative
+# error per operand; its measured error is asserted against a looser bound.
+SPLIT_TOL = {"p32": 1e-8, "pb6": 1e-8, "pb3": 1e-6}
+
+
+@pytest.mark.parametrize("prec", ["p32", "pb3", "pb6"])
+def test_split_precision_blocks(prec):
+    w = W()
+    pl = w.plan_std("3He")
+    hu, hd, du, dd = props(9, 1, (3, 3, 3, 2))
+    B = w.blocks(pl, du, dd, prec).cpu().numpy()
+    for t in range(2):
+        ref = oracle_blocks(ops.helium3(), hu, hd, 0, t)
+        got = B[0, t, ..., 0] + 1j * B[0, t, ..., 1]
+        rel = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        assert rel <= {"p32": 1e-5, "pb3": 1e-3, "pb6": 1e-5}[prec], (prec, t, rel)
+
+
+@pytest.mark.parametrize("prec", ["p32", "pb3", "pb6"])
+@pytest.mark.parametrize("name,dims", [("2H", (4, 4, 4, 8)), ("3He", (3, 3, 2, 3))])
+def test_split_precision_correlator_bound(prec, name, dims):
+    w = W()
+    pl = w.plan_std(name)
+    hu, hd, du, dd = props(10, 1, dims)
+    C = w.contract(pl, w.blocks(pl, du, dd, prec)).cpu().numpy()
+    check_C(ops.by_name(name), pl, C, hu, hd, range(dims[3]), tol=SPLIT_TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["p32", "pb6"])
+def test_split_precision_late_time_slices(prec):
+    # |S| ~ exp(-0.5 t): at t = 63 a product of three entries is ~1e-41, below the
+    # FP32 normal range; the per-chunk power-of-two scaling keeps it exact in range
+    w = W()
+    pl = w.plan_std("2H")
+    hu, hd, du, dd = props(11, 1, (2, 2, 2, 64))
+    C = w.contract(pl, w.blocks(pl, du, dd, prec)).cpu().numpy()
+    check_C(ops.deuteron(), pl, C, hu, hd, [40, 63], tol=SPLIT_TOL[prec])
