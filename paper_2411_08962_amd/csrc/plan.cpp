@@ -134,11 +134,64 @@ struct Group {
     GInt w;
 };
 
-struct Rec {
-    std::array<uint64_t, 2 * kMaxTrials> h;
-    std::array<uint16_t, kMaxA> rep;
-    GInt c;     // coefficient times the normalisation sign
-    int8_t s;   // normalisation sign of this monomial's hash
+
+// Open-addressing table of the distinct monomials of one group, keyed exactly
+// by the sorted (kind*792 + index) tuple of the term (equal tuples are the same
+// monomial), accumulating the exact signed coefficients.
+struct SynSlot {
+    unsigned __int128 key;  // 0 marks an empty slot (tuples are stored + 1)
+    __int128 re, im;
+};
+struct SynTable {
+    std::vector<SynSlot> slots;
+    size_t n = 0;
+    void reset()
+    {
+        if (slots.size() != (1u << 16)) slots.assign(1u << 16, SynSlot{0, 0, 0});
+        else
+            for (auto &x : slots) x.key = 0;
+        n = 0;
+    }
+    static uint64_t mix(unsigned __int128 k)
+    {
+        uint64_t x = (uint64_t)k ^ ((uint64_t)(k >> 64) * 0x9E3779B97F4A7C15ULL);
+        x ^= x >> 31;
+        x *= 0xBF58476D1CE4E5B9ULL;
+        x ^= x >> 27;
+        return x;
+    }
+    void insert(unsigned __int128 key, __int128 re, __int128 im)
+    {
+        const size_t mask = slots.size() - 1;
+        size_t i = mix(key) & mask;
+        for (;;) {
+            SynSlot &x = slots[i];
+            if (x.key == 0) {
+                x.key = key;
+                x.re = re;
+                x.im = im;
+                ++n;
+                return;
+            }
+            if (x.key == key) {
+                x.re += re;
+                x.im += im;
+                return;
+            }
+            i = (i + 1) & mask;
+        }
+    }
+    void add(unsigned __int128 key, GInt c)
+    {
+        if (2 * (n + 1) > slots.size()) {
+            std::vector<SynSlot> old(slots.size() * 2, SynSlot{0, 0, 0});
+            old.swap(slots);
+            n = 0;
+            for (auto &x : old)
+                if (x.key) insert(x.key, x.re, x.im);
+        }
+        insert(key, c.re, c.im);
+    }
 };
 
 struct Ctx {
@@ -153,7 +206,7 @@ struct Enumerator {
     const Ctx &cx;
     const std::vector<std::vector<F>> &bh;        // [trial][kind*792 + c]
     const std::vector<uint8_t> &zero_entry;       // [kind*792 + c] identically zero
-    std::vector<Rec> recs;
+    SynTable table;
     int64_t n_enum = 0;
 
     // current group
@@ -167,30 +220,16 @@ struct Enumerator {
 
     int val(int flav, int p) const { return flav == 0 ? g->U[p] : g->D[p]; }
 
-    void rec(int a, uint32_t used_u, uint32_t used_d, int inv, const F *hp)
+    void rec(int a, uint32_t used_u, uint32_t used_d, int inv)
     {
         if (a == cx.A) {
             ++n_enum;
-            Rec r;
-            int first = -1;
-            for (int t = 0; t < cx.trials; ++t)
-                if (!hp[t].zero()) { first = t; break; }
-            if (first < 0) return;  // identically zero monomial
-            bool neg = hp[first].negative();
-            for (int t = 0; t < cx.trials; ++t) {
-                F v = neg ? hp[t].neg() : hp[t];
-                r.h[2 * t] = v.k0();
-                r.h[2 * t + 1] = v.k1();
-            }
-            for (int t = cx.trials; t < kMaxTrials; ++t) r.h[2 * t] = r.h[2 * t + 1] = 0;
-            std::array<uint16_t, kMaxA> s = idx;
-            std::sort(s.begin(), s.begin() + cx.A);
-            for (int q = cx.A; q < kMaxA; ++q) s[q] = 0xFFFF;
-            r.rep = s;
-            r.s = neg ? -1 : 1;
-            int sg = ((inv & 1) ? -1 : 1) * pat->eta * r.s;
-            r.c = GInt{sg * coef0.re, sg * coef0.im};
-            recs.push_back(r);
+            std::array<uint16_t, kMaxA> srt = idx;
+            std::sort(srt.begin(), srt.begin() + cx.A);
+            unsigned __int128 key = 0;
+            for (int q = 0; q < cx.A; ++q) key = (key << 16) | (unsigned __int128)(srt[q] + 1);
+            const int sg = ((inv & 1) ? -1 : 1) * pat->eta;
+            table.add(key, GInt{sg * coef0.re, sg * coef0.im});
             return;
         }
         const int k = pat->k[a];
@@ -199,7 +238,6 @@ struct Enumerator {
         const int nf = f == 0 ? cx.nu : cx.nd, ng = gfl == 0 ? cx.nu : cx.nd;
         uint32_t uf = f == 0 ? used_u : used_d;
         uint32_t ug = gfl == 0 ? used_u : used_d;
-        F hn[kMaxTrials];
         for (int p0 = 0; p0 < nf; ++p0) {
             if ((uf >> p0) & 1) continue;
             uint32_t uf0 = uf | (1u << p0);
@@ -216,10 +254,9 @@ struct Enumerator {
                     int c = pair_index(i1, i3) * 12 + i2;
                     int e = k * kBlockLen + c;
                     if (zero_entry[e]) continue;
-                    for (int t = 0; t < cx.trials; ++t) hn[t] = hp[t] * bh[t][e];
                     idx[a] = (uint16_t)e;
                     uint32_t nu_ = f == 0 ? uf2 : ug1, nd_ = f == 0 ? ug1 : uf2;
-                    rec(a + 1, nu_, nd_, inv + inv0 + inv1 + inv2, hn);
+                    rec(a + 1, nu_, nd_, inv + inv0 + inv1 + inv2);
                 }
             }
         }
@@ -228,16 +265,12 @@ struct Enumerator {
     void run_group(const Group &grp)
     {
         g = &grp;
-        F one;
-        one = F::from(GInt{1, 0});
-        F h0[kMaxTrials];
-        for (int t = 0; t < kMaxTrials; ++t) h0[t] = one;
         for (const Pattern &p : cx.snk) {
             pat = &p;
             bool ovf = false;
             coef0 = gmul(p.c, grp.w, ovf);
             if (ovf) throw std::runtime_error("coefficient overflow");
-            rec(0, 0, 0, 0, h0);
+            rec(0, 0, 0, 0);
         }
     }
 };
@@ -248,32 +281,69 @@ struct Term {
 };
 
 // Merge records of one group: equal normalised hashes in every trial.
-void merge(std::vector<Rec> &recs, int trials, std::vector<Term> &out)
+// Second level: evaluate each distinct monomial on the random F_p propagators
+// and merge monomials whose values agree up to sign in every trial (identity
+// testing, App. C); the representative is the smallest tuple, with its sign.
+template <class F>
+void merge(const SynTable &tb, const Ctx &cx, const std::vector<std::vector<F>> &bh, std::vector<Term> &out)
 {
-    auto key_less = [trials](const Rec &x, const Rec &y) {
-        for (int t = 0; t < 2 * trials; ++t)
+    struct R {
+        std::array<uint64_t, 2 * kMaxTrials> h;
+        std::array<uint16_t, kMaxA> rep;
+        __int128 re, im;
+        int8_t s;
+    };
+    std::vector<R> rs;
+    rs.reserve(tb.n);
+    for (const SynSlot &x : tb.slots) {
+        if (!x.key || (x.re == 0 && x.im == 0)) continue;
+        R r{};
+        unsigned __int128 k = x.key;
+        for (int q = cx.A - 1; q >= 0; --q) {
+            r.rep[q] = (uint16_t)((uint16_t)(k & 0xFFFF) - 1);
+            k >>= 16;
+        }
+        for (int q = cx.A; q < kMaxA; ++q) r.rep[q] = 0xFFFF;
+        F hv[kMaxTrials];
+        int first = -1;
+        for (int t = 0; t < cx.trials; ++t) {
+            F v = bh[t][r.rep[0]];
+            for (int q = 1; q < cx.A; ++q) v = v * bh[t][r.rep[q]];
+            hv[t] = v;
+            if (first < 0 && !v.zero()) first = t;
+        }
+        if (first < 0) continue;  // identically zero monomial
+        const bool neg = hv[first].negative();
+        for (int t = 0; t < cx.trials; ++t) {
+            F v = neg ? hv[t].neg() : hv[t];
+            r.h[2 * t] = v.k0();
+            r.h[2 * t + 1] = v.k1();
+        }
+        r.s = neg ? -1 : 1;
+        r.re = x.re * r.s;
+        r.im = x.im * r.s;
+        rs.push_back(r);
+    }
+    const int nk = 2 * cx.trials;
+    std::sort(rs.begin(), rs.end(), [nk](const R &x, const R &y) {
+        for (int t = 0; t < nk; ++t)
             if (x.h[t] != y.h[t]) return x.h[t] < y.h[t];
         return x.rep < y.rep;
-    };
-    std::sort(recs.begin(), recs.end(), key_less);
-    size_t i = 0;
-    while (i < recs.size()) {
+    });
+    const __int128 lim = ((__int128)1) << 62;
+    for (size_t i = 0; i < rs.size();) {
         size_t j = i;
-        GAcc acc;
-        while (j < recs.size() &&
-               std::equal(recs[j].h.begin(), recs[j].h.begin() + 2 * trials, recs[i].h.begin())) {
-            acc.add(recs[j].c, 1);
+        __int128 re = 0, im = 0;
+        while (j < rs.size() && std::equal(rs[j].h.begin(), rs[j].h.begin() + nk, rs[i].h.begin())) {
+            re += rs[j].re;
+            im += rs[j].im;
             ++j;
         }
-        // representative: smallest rep (first after the sort), with its own sign
-        int s = recs[i].s;
-        if (acc.re != 0 || acc.im != 0) {
-            const __int128 lim = ((__int128)1) << 62;
-            if (acc.re > lim || acc.re < -lim || acc.im > lim || acc.im < -lim)
-                throw std::runtime_error("merged coefficient overflow");
+        if (re != 0 || im != 0) {
+            if (re > lim || re < -lim || im > lim || im < -lim) throw std::runtime_error("merged coefficient overflow");
             Term t;
-            t.rep = recs[i].rep;
-            t.c = GInt{(int64_t)(s * acc.re), (int64_t)(s * acc.im)};
+            t.rep = rs[i].rep;
+            t.c = GInt{(int64_t)(rs[i].s * re), (int64_t)(rs[i].s * im)};
             out.push_back(t);
         }
         i = j;
@@ -349,11 +419,11 @@ void enumerate_all(const Ctx &cx, const std::vector<std::vector<F>> &bh, const s
             size_t gi = next.fetch_add(1);
             if (gi >= ng || bad.load()) break;
             try {
-                en.recs.clear();
+                en.table.reset();
                 en.n_enum = 0;
                 en.run_group(cx.groups[gi]);
                 enum_count[gi] = en.n_enum;
-                merge(en.recs, cx.trials, per_group[gi]);
+                merge(en.table, cx, bh, per_group[gi]);
             } catch (const std::exception &e) {
                 std::lock_guard<std::mutex> lk(emu);
                 err = e.what();
