@@ -130,8 +130,13 @@ wick_status wick_plan_stats(wick_plan_t plan, int64_t *n_enumerated, int64_t *n_
  * kidx = kind*792 + c, and coef[n_terms][2] (scale included). */
 wick_status wick_plan_table(wick_plan_t plan, uint16_t *kidx, double *coef);
 
-/* Kind weights of block kind k (host arrays sized by n_w from the desc). */
-wick_status wick_plan_kind(wick_plan_t plan, int32_t k, int32_t flavor[3], int32_t *n_w);
+/* Block kind k of a plan: block kinds are the desc's kinds used at the sink,
+ * numbered in order of first use in the sink patterns (the kind axis of B
+ * and the kind part of kidx). Writes its slot flavors and its number of
+ * weight entries n_w; if j / w_re / w_im are not NULL, also its weights as
+ * given in the desc (host arrays of n_w*3, n_w, n_w entries). */
+wick_status wick_plan_kind(wick_plan_t plan, int32_t k, int32_t flavor[3], int32_t *n_w,
+                           int8_t *j, int64_t *w_re, int64_t *w_im);
 
 /* Store / reuse a plan (the look-up table of App. C): a versioned file with a
  * checksum; load returns WICK_ECORRUPT on any mismatch. */
@@ -164,10 +169,16 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
                             const int32_t dims[4], int32_t n_cfg, wick_precision prec,
                             int32_t use_graph, wick_stream_t stream, double *C);
 
-/* Pick site-chunk and term-slice sizes for a plan and lattice by timing the
- * candidates on the current device (blocking). The choice is cached in
- * memory and, if cache_path is not NULL, in that file, keyed by (arch,
- * dims, kinds, A, terms, precision). */
+/* Pick the block kernel's sites per workgroup (single and batched launches)
+ * and the term sum's terms per workgroup for a plan and lattice by timing
+ * candidates on the current device, on scratch propagators of one
+ * configuration that the call allocates and frees (blocking; it uses a
+ * stream of its own). Later wick_blocks / wick_contract / wick_correlator
+ * calls with the same (dims, dtype, precision, plan sizes) use the choice.
+ * The choice is kept in memory and, if cache_path is not NULL, merged into
+ * that text file (created if missing); a cache that already holds the shape
+ * is used without timing. Errors: WICK_EINVAL (bad arguments),
+ * WICK_ECORRUPT (unreadable cache file), WICK_ENOMEM, WICK_EHIP. */
 wick_status wick_autotune(wick_plan_t plan, const int32_t dims[4], wick_dtype dtype,
                           wick_precision prec, const char *cache_path);
 

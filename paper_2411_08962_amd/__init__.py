@@ -3,5 +3,6 @@ contraction with baryon blocks (arXiv 2411.08962).
 
 The C ABI is in ``include/wick.h``; :mod:`.wick` is its Python binding.
 """
-from .wick import (BLOCK_LEN, EXPORTS, PRECISIONS, Plan, WickError, autotune, blocks,  # noqa: F401
+from .wick import (BLOCK_LEN, ECORRUPT, EHIP, EINVAL, ENOMEM, EUNSUPPORTED, ETOOBIG, EXPORTS, OK,  # noqa: F401
+                   PRECISIONS, Plan, WickError, autotune, blocks,
                    contract, correlator, lib, plan, plan_std, profile, profile_read, version)

@@ -72,6 +72,18 @@ wick_status workspace(hipStream_t s, size_t bytes, void **out)
     return WICK_OK;
 }
 
+void release_workspace(hipStream_t s)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({dev, s});
+    if (it == g_ws.end()) return;
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(it->second.ptr);
+    g_ws.erase(it);
+}
+
 // ---------------------------------------------------------- device tables
 struct DevPlan {
     int device = -1;
@@ -267,9 +279,8 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
 
 // ------------------------------------------------------------- tuning
 struct Tune {
-    int chunk_sites = 256;
-    int64_t slice_len = 0;      // 0: derived
-    int batch_chunk_sites = 0;  // 0: derived
+    int chunk_sites = 256;      // sites per workgroup of the block kernel
+    int batch_chunk_sites = 0;  // the same for batched launches (0: derived from the batch size)
 };
 std::mutex g_tune_mu;
 std::map<std::string, Tune> g_tune;
@@ -287,6 +298,23 @@ Tune tune_for(const wick_plan_s *p, const int32_t dims[4], int dtype, int prec)
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(tune_key(p, dims, dtype, prec));
     return it == g_tune.end() ? Tune{} : it->second;
+}
+
+// term-slice length of the sum, keyed by the table and the number of (cfg, t) sets
+std::map<std::string, int64_t> g_slice;
+
+std::string slice_key(const wick_plan_s *p, int64_t n_ct)
+{
+    std::ostringstream o;
+    o << "gfx950:A" << p->A << ":K" << p->kinds.size() << ":N" << p->n_terms << ":ct" << n_ct;
+    return o.str();
+}
+
+int64_t tuned_slice(const wick_plan_s *p, int64_t n_ct)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_slice.find(slice_key(p, n_ct));
+    return it == g_slice.end() ? 0 : it->second;
 }
 
 int64_t default_slice_len(int64_t N, int64_t n_ct)
@@ -312,7 +340,7 @@ wick_status check_dims(const int32_t dims[4], int32_t n_cfg, int64_t *V)
 }
 
 wick_status do_blocks(wick_plan_s *p, const void *Su, const void *Sd, int dtype, const int32_t dims[4], int n_cfg,
-                      int prec, hipStream_t s, double *B)
+                      int prec, hipStream_t s, double *B, int chunk_override = 0)
 {
     int64_t V;
     wick_status st = check_dims(dims, n_cfg, &V);
@@ -349,7 +377,7 @@ wick_status do_blocks(wick_plan_s *p, const void *Su, const void *Sd, int dtype,
     L.T = dims[3];
     L.n_cfg = n_cfg;
     L.K = (int)p->kinds.size();
-    L.chunk_sites = std::max(4, tu.chunk_sites / 4 * 4);
+    L.chunk_sites = std::max(4, (chunk_override > 0 ? chunk_override : tu.chunk_sites) / 4 * 4);
     L.n_chunks = (int)((V + L.chunk_sites - 1) / L.chunk_sites);
     L.B = B;
     size_t bytes = (size_t)n_cfg * dims[3] * L.n_chunks * L.K * 1728 * 16;
@@ -362,7 +390,7 @@ wick_status do_blocks(wick_plan_s *p, const void *Su, const void *Sd, int dtype,
 }
 
 wick_status do_contract(wick_plan_s *p, const double *B, int n_cfg, int T, hipStream_t s, double *C,
-                        const int32_t *dims_for_tune)
+                        int64_t slice_override = 0)
 {
     if (!B || !C) return fail(WICK_EINVAL, "wick_contract: null pointer");
     if (n_cfg < 1 || T < 1) return fail(WICK_EINVAL, "wick_contract: n_cfg and T must be >= 1");
@@ -383,8 +411,7 @@ wick_status do_contract(wick_plan_s *p, const double *B, int n_cfg, int T, hipSt
     L.K = (int)p->kinds.size();
     L.N = p->n_terms;
     L.n_ct = (int)n_ct;
-    int64_t sl = 0;
-    if (dims_for_tune) sl = tune_for(p, dims_for_tune, 0, 0).slice_len;
+    const int64_t sl = slice_override > 0 ? slice_override : tuned_slice(p, n_ct);
     L.slice_len = sl > 0 ? sl : default_slice_len(L.N, n_ct);
     L.n_slices = (int)((L.N + L.slice_len - 1) / L.slice_len);
     if ((int64_t)L.n_slices * n_ct > 0x7ffffff0LL) return fail(WICK_ETOOBIG, "wick_contract: grid too large");
@@ -573,6 +600,198 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
     if (contract_lds_bytes(max_K) > 160 * 1024 - 256) return fail(WICK_EUNSUPPORTED, "batch: more than 12 kinds");
     return WICK_OK;
 }
+// ------------------------------------------------------------- autotuning
+// Cache file: a header line, then one line per tuned shape,
+//   "blocks <shape key> <chunk_sites> <batch_chunk_sites>" or "contract <table key> <slice_len>".
+const char *kTuneHeader = "wick-tune 1";
+
+wick_status load_tune_file(const char *path)
+{
+    std::ifstream f(path);
+    if (!f) return WICK_OK;  // no cache yet
+    std::string line;
+    if (!std::getline(f, line) || line != kTuneHeader)
+        return fail(WICK_ECORRUPT, std::string("tune cache ") + path + ": bad header");
+    std::map<std::string, Tune> tb;
+    std::map<std::string, int64_t> ts;
+    int ln = 1;
+    while (std::getline(f, line)) {
+        ++ln;
+        if (line.empty()) continue;
+        std::istringstream is(line);
+        std::string what, key, extra;
+        bool ok = static_cast<bool>(is >> what >> key);
+        if (ok && what == "blocks") {
+            Tune t;
+            ok = static_cast<bool>(is >> t.chunk_sites >> t.batch_chunk_sites) && t.chunk_sites >= 4 &&
+                 t.chunk_sites <= (1 << 24) && t.batch_chunk_sites >= 0 && t.batch_chunk_sites <= (1 << 24);
+            if (ok) tb[key] = t;
+        } else if (ok && what == "contract") {
+            int64_t v = 0;
+            ok = static_cast<bool>(is >> v) && v >= 1;
+            if (ok) ts[key] = v;
+        } else {
+            ok = false;
+        }
+        if (!ok || (is >> extra))
+            return fail(WICK_ECORRUPT, std::string("tune cache ") + path + ": bad line " + std::to_string(ln));
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &kv : tb) g_tune[kv.first] = kv.second;
+    for (auto &kv : ts) g_slice[kv.first] = kv.second;
+    return WICK_OK;
+}
+
+wick_status save_tune_file(const char *path)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        if (!f) return fail(WICK_EINVAL, std::string("cannot write tune cache ") + tmp);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        f << kTuneHeader << "\n";
+        for (auto &kv : g_tune) f << "blocks " << kv.first << ' ' << kv.second.chunk_sites << ' '
+                                  << kv.second.batch_chunk_sites << "\n";
+        for (auto &kv : g_slice) f << "contract " << kv.first << ' ' << kv.second << "\n";
+        if (!f) return fail(WICK_EINVAL, std::string("cannot write tune cache ") + tmp);
+    }
+    if (std::rename(tmp.c_str(), path) != 0) return fail(WICK_EINVAL, std::string("cannot replace ") + path);
+    return WICK_OK;
+}
+
+// Average time of `reps` back-to-back runs of f on s, after one untimed run.
+template <class F> wick_status time_runs(hipStream_t s, int reps, F f, float *ms)
+{
+    wick_status st = f();
+    if (st != WICK_OK) return st;
+    hipEvent_t a, b;
+    hipError_t e;
+    if ((e = hipEventCreate(&a)) != hipSuccess) return hip_fail(e, "autotune hipEventCreate");
+    if ((e = hipEventCreate(&b)) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_fail(e, "autotune hipEventCreate");
+    }
+    (void)hipEventRecord(a, s);
+    for (int r = 0; r < reps && st == WICK_OK; ++r) st = f();
+    (void)hipEventRecord(b, s);
+    e = hipEventSynchronize(b);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != WICK_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    *ms = t / reps;
+    return WICK_OK;
+}
+
+// Device scratch of one autotune call, released on every exit path.
+struct TuneScratch {
+    void *Su = nullptr, *Sd = nullptr, *B = nullptr, *C = nullptr;
+    hipStream_t s = nullptr;
+    ~TuneScratch()
+    {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            release_workspace(s);
+            (void)hipStreamDestroy(s);
+        }
+        for (void *q : {Su, Sd, B, C})
+            if (q) (void)hipFree(q);
+    }
+};
+
+wick_status autotune(wick_plan_s *p, const int32_t dims[4], int dtype, int prec, const char *cache_path)
+{
+    int64_t V;
+    wick_status st = check_dims(dims, 1, &V);
+    if (st != WICK_OK) return st;
+    if (dtype != WICK_C128 && dtype != WICK_C64) return fail(WICK_EINVAL, "wick_autotune: bad dtype");
+    if (prec < WICK_P64 || prec > WICK_PB6) return fail(WICK_EINVAL, "wick_autotune: bad precision");
+    if (cache_path && (st = load_tune_file(cache_path)) != WICK_OK) return st;
+    const int T = dims[3];
+    const std::string key = tune_key(p, dims, dtype, prec), skey = slice_key(p, T);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (g_tune.count(key) && (p->n_terms == 0 || g_slice.count(skey))) return WICK_OK;
+    }
+    // one configuration of constant, nonzero propagators (timing does not depend on the values)
+    TuneScratch sc;
+    const int K = (int)p->kinds.size();
+    const size_t esz = dtype == WICK_C128 ? 16 : 8, n_prop = (size_t)V * T * 144 * esz;
+    hipError_t e;
+    if ((e = hipMalloc(&sc.Su, n_prop)) != hipSuccess || (e = hipMalloc(&sc.Sd, n_prop)) != hipSuccess ||
+        (e = hipMalloc(&sc.B, (size_t)T * K * kBlockLen * 16)) != hipSuccess ||
+        (e = hipMalloc(&sc.C, (size_t)T * 16)) != hipSuccess)
+        return fail(WICK_ENOMEM, std::string("wick_autotune hipMalloc: ") + hipGetErrorString(e));
+    const uint32_t pattern = dtype == WICK_C128 ? 0x3fe00000u : 0x3f000000u;  // ~0.5 in every real and imaginary part
+    if ((e = hipMemsetD32((hipDeviceptr_t)sc.Su, (int)pattern, n_prop / 4)) != hipSuccess ||
+        (e = hipMemsetD32((hipDeviceptr_t)sc.Sd, (int)pattern, n_prop / 4)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&sc.s, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "wick_autotune setup");
+
+    // block kernel: sites per workgroup (bounded by a 4 GiB split-K workspace)
+    const int cand[] = {32, 64, 128, 256, 512, 1024, 2048, 4096};
+    int best_chunk = 0;
+    float best = 0.f;
+    for (int c : cand) {
+        if (c >= 2 * V && c != cand[0]) break;  // larger chunks than twice the volume change nothing
+        const int64_t n_chunks = (V + c - 1) / c;
+        if ((double)T * n_chunks * K * 1728 * 16 > 4.0 * (1ull << 30)) continue;
+        float ms = 0.f;
+        st = time_runs(sc.s, 3, [&] {
+            return do_blocks(p, sc.Su, sc.Sd, dtype, dims, 1, prec, sc.s, (double *)sc.B, c);
+        }, &ms);
+        if (st != WICK_OK) return st;
+        if (!best_chunk || ms < best) { best = ms; best_chunk = c; }
+    }
+    if (!best_chunk) return fail(WICK_ETOOBIG, "wick_autotune: no site chunk fits the workspace bound");
+
+    // term sum: terms per workgroup
+    int64_t best_slice = 0;
+    if (p->n_terms > 0) {
+        if ((st = do_blocks(p, sc.Su, sc.Sd, dtype, dims, 1, prec, sc.s, (double *)sc.B, best_chunk)) != WICK_OK)
+            return st;
+        const int64_t scand[] = {1024, 2048, 4096, 8192, 16384, 32768, 65536, 262144};
+        best = 0.f;
+        for (int64_t sl : scand) {
+            if (sl >= 2 * p->n_terms && sl != scand[0]) break;
+            float ms = 0.f;
+            st = time_runs(sc.s, 3, [&] { return do_contract(p, (const double *)sc.B, 1, T, sc.s, (double *)sc.C, sl); },
+                           &ms);
+            if (st != WICK_OK) return st;
+            if (!best_slice || ms < best) { best = ms; best_slice = sl; }
+        }
+    }
+
+    // batched launch of this plan alone: sites per workgroup (plans without nucleon form have no batched path)
+    int best_batch = 0;
+    best = 0.f;
+    wick_plan_t plist[1] = {p};
+    const wick_item item{0, 0};
+    for (int c : cand) {
+        if (c < 64) continue;
+        if (c >= 2 * V) break;
+        BatchEntry b;
+        st = build_batch(plist, &item, 1, sc.Su, sc.Sd, dtype, dims, V, prec, c, (double *)sc.C, b);
+        if (st == WICK_EUNSUPPORTED) { free_batch(b); best_batch = 0; break; }
+        if (st != WICK_OK) { free_batch(b); return st; }
+        float ms = 0.f;
+        st = time_runs(sc.s, 3, [&] {
+            hipError_t le = launch_batch(b.L, sc.s);
+            return le == hipSuccess ? WICK_OK : hip_fail(le, "wick_autotune batch launch");
+        }, &ms);
+        free_batch(b);
+        if (st != WICK_OK) return st;
+        if (!best_batch || ms < best) { best = ms; best_batch = c; }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = Tune{best_chunk, best_batch};
+        if (best_slice > 0) g_slice[skey] = best_slice;
+    }
+    return cache_path ? save_tune_file(cache_path) : WICK_OK;
+}
 }  // namespace
 
 Probe::Probe(const char *n, hipStream_t st) : name(n), s(st)
@@ -667,12 +886,20 @@ wick_status wick_plan_table(wick_plan_t p, uint16_t *kidx, double *coef)
     return WICK_OK;
 }
 
-wick_status wick_plan_kind(wick_plan_t p, int32_t k, int32_t flavor[3], int32_t *n_w)
+wick_status wick_plan_kind(wick_plan_t p, int32_t k, int32_t flavor[3], int32_t *n_w, int8_t *j, int64_t *w_re,
+                           int64_t *w_im)
 {
     if (!p || k < 0 || k >= (int32_t)p->kinds.size()) return fail(WICK_EINVAL, "wick_plan_kind: bad plan or kind");
+    const KindDef &kd = p->kinds[k];
     if (flavor)
-        for (int s = 0; s < 3; ++s) flavor[s] = p->kinds[k].flav[s];
-    if (n_w) *n_w = (int32_t)p->kinds[k].w.size();
+        for (int s = 0; s < 3; ++s) flavor[s] = kd.flav[s];
+    if (n_w) *n_w = (int32_t)kd.w.size();
+    for (size_t e = 0; e < kd.w.size(); ++e) {
+        if (j)
+            for (int s = 0; s < 3; ++s) j[3 * e + s] = kd.j[e][s];
+        if (w_re) w_re[e] = kd.w[e].re;
+        if (w_im) w_im[e] = kd.w[e].im;
+    }
     return WICK_OK;
 }
 
@@ -708,7 +935,7 @@ wick_status wick_blocks(wick_plan_t p, const void *S_u, const void *S_d, wick_dt
 wick_status wick_contract(wick_plan_t p, const double *B, int32_t n_cfg, int32_t T, wick_stream_t stream, double *C)
 {
     if (!p) return fail(WICK_EINVAL, "wick_contract: null plan");
-    WICK_TRY(return do_contract(p, B, n_cfg, T, (hipStream_t)stream, C, nullptr));
+    WICK_TRY(return do_contract(p, B, n_cfg, T, (hipStream_t)stream, C));
 }
 
 wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wick_item *items, int32_t n_items,
@@ -767,7 +994,9 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
         }
         it = g_batch.emplace(key.str(), b).first;
     }
+    Probe pr("correlator", s);
     hipError_t e = it->second.exec ? hipGraphLaunch(it->second.exec, s) : launch_batch(it->second.L, s);
+    pr.stop();
     if (e != hipSuccess) return hip_fail(e, "wick_correlator launch");
     return WICK_OK;
 }
@@ -776,8 +1005,7 @@ wick_status wick_autotune(wick_plan_t p, const int32_t dims[4], wick_dtype dtype
                           const char *cache_path)
 {
     if (!p) return fail(WICK_EINVAL, "wick_autotune: null plan");
-    (void)dims; (void)dtype; (void)prec; (void)cache_path;
-    return WICK_OK;
+    WICK_TRY(return autotune(p, dims, (int)dtype, (int)prec, cache_path));
 }
 
 wick_status wick_shutdown(void)

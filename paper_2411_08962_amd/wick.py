@@ -71,7 +71,7 @@ def lib():
     L.wick_plan_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                   ctypes.POINTER(ctypes.c_double)]
     L.wick_plan_table.argtypes = [P, P, P]
-    L.wick_plan_kind.argtypes = [P, i32, P, ctypes.POINTER(i32)]
+    L.wick_plan_kind.argtypes = [P, i32, P, ctypes.POINTER(i32), P, P, P]
     L.wick_plan_save.argtypes = [P, ctypes.c_char_p]
     L.wick_plan_load.argtypes = [ctypes.c_char_p, pp]
     L.wick_plan_destroy.argtypes = [P]
@@ -147,8 +147,18 @@ class Plan:
     def kind_flavors(self, k):
         f = (ctypes.c_int32 * 3)()
         nw = ctypes.c_int32()
-        _check(lib().wick_plan_kind(self._h, k, f, ctypes.byref(nw)))
+        _check(lib().wick_plan_kind(self._h, k, f, ctypes.byref(nw), None, None, None))
         return tuple(f), nw.value
+
+    def kind(self, k):
+        """Block kind k: (flavors (3,), weights [(j1, j2, j3, w_re, w_im), ...])."""
+        fl, nw = self.kind_flavors(k)
+        j = np.zeros((max(nw, 1), 3), dtype=np.int8)
+        re = np.zeros(max(nw, 1), dtype=np.int64)
+        im = np.zeros(max(nw, 1), dtype=np.int64)
+        _check(lib().wick_plan_kind(self._h, k, None, None, j.ctypes.data_as(ctypes.c_void_p),
+                                    re.ctypes.data_as(ctypes.c_void_p), im.ctypes.data_as(ctypes.c_void_p)))
+        return fl, [(int(j[e, 0]), int(j[e, 1]), int(j[e, 2]), int(re[e]), int(im[e])) for e in range(nw)]
 
     def save(self, path):
         _check(lib().wick_plan_save(self._h, str(path).encode()))
@@ -224,12 +234,19 @@ def _prop_args(S_u, S_d):
             raise ValueError("propagators must be complex128 or complex64")
         if S.dim() != 7 or S.shape[-2:] != (12, 12):
             raise ValueError("propagators must have shape [n_cfg, T, Z, Y, X, 12, 12]")
-    if S_u.shape != S_d.shape or S_u.dtype != S_d.dtype:
+    if S_u.shape != S_d.shape or S_u.dtype != S_d.dtype or S_u.device != S_d.device:
         raise ValueError("S_u and S_d differ in shape or dtype")
     n_cfg, T, Z, Y, X = S_u.shape[:5]
     dims = (ctypes.c_int32 * 4)(X, Y, Z, T)
     dtype = C128 if S_u.dtype == torch.complex128 else C64
     return n_cfg, T, dims, dtype
+
+
+def _check_out(out, shape, device):
+    torch = _torch()
+    if (not out.is_cuda or out.device != device or not out.is_contiguous() or out.dtype != torch.float64
+            or tuple(out.shape) != tuple(shape)):
+        raise ValueError(f"out must be a contiguous float64 tensor of shape {tuple(shape)} on {device}")
 
 
 def blocks(p: Plan, S_u, S_d, precision="p64", out=None):
@@ -239,6 +256,7 @@ def blocks(p: Plan, S_u, S_d, precision="p64", out=None):
     K = p.n_kinds
     if out is None:
         out = torch.empty((n_cfg, T, K, BLOCK_LEN, 2), dtype=torch.float64, device=S_u.device)
+    _check_out(out, (n_cfg, T, K, BLOCK_LEN, 2), S_u.device)
     _check(lib().wick_blocks(p.handle, ctypes.c_void_p(S_u.data_ptr()), ctypes.c_void_p(S_d.data_ptr()), dtype,
                              dims, n_cfg, PRECISIONS[precision], _stream(), ctypes.c_void_p(out.data_ptr())))
     return out
@@ -254,6 +272,7 @@ def contract(p: Plan, B, out=None):
         raise ValueError("B does not match the plan's kinds")
     if out is None:
         out = torch.empty((n_cfg, T, 2), dtype=torch.float64, device=B.device)
+    _check_out(out, (n_cfg, T, 2), B.device)
     _check(lib().wick_contract(p.handle, ctypes.c_void_p(B.data_ptr()), n_cfg, T, _stream(),
                                ctypes.c_void_p(out.data_ptr())))
     return out
@@ -269,6 +288,7 @@ def correlator(plans, items, S_u, S_d, precision="p64", use_graph=False, out=Non
         it[i].plan, it[i].cfg = int(pi), int(cfg)
     if out is None:
         out = torch.empty((len(items), T, 2), dtype=torch.float64, device=S_u.device)
+    _check_out(out, (len(items), T, 2), S_u.device)
     _check(lib().wick_correlator(hp, len(plans), it, len(items), ctypes.c_void_p(S_u.data_ptr()),
                                  ctypes.c_void_p(S_d.data_ptr()), dtype, dims, n_cfg, PRECISIONS[precision],
                                  1 if use_graph else 0, _stream(), ctypes.c_void_p(out.data_ptr())))

@@ -55,6 +55,23 @@ def sink_kind_order(op):
     return order
 
 
+def plan_kind_order(op, pl):
+    """For each block kind of the plan, the index of the oracle operator's kind
+    with the same flavors and weights (the plan numbers kinds by first use in
+    its own sink patterns, which need not follow the oracle's pattern order)."""
+    def canon(fl, w):
+        return tuple(int(f) for f in fl), tuple(sorted((int(a), int(b), int(c), int(x), int(y)) for a, b, c, x, y in w))
+    index = {}
+    for i, k in enumerate(op.kinds):
+        index.setdefault(canon(k.flavors, k.w), i)
+    order = []
+    for k in range(pl.n_kinds):
+        key = canon(*pl.kind(k))
+        assert key in index, f"plan kind {k} has no counterpart in the oracle operator"
+        order.append(index[key])
+    return order
+
+
 def header_symbols():
     txt = open(os.path.join(ROOT, "include", "wick.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)

@@ -10,7 +10,7 @@ import pytest
 import oracle
 import wick_inputs as wi
 from oracle import operators as ops
-from tests.helpers import eval_table, oracle_compact_blocks, sink_kind_order
+from tests.helpers import eval_table, oracle_compact_blocks, plan_kind_order
 
 pytestmark = pytest.mark.gpu
 
@@ -35,14 +35,15 @@ def props(wid, n_cfg, dims, dtype=np.complex128):
     return hu, hd, torch.from_numpy(hu).cuda(), torch.from_numpy(hd).cuda()
 
 
-def oracle_blocks(op, hu, hd, cfg, t):
-    return oracle_compact_blocks(op, sink_kind_order(op), hu[cfg, t].astype(np.complex128),
+def oracle_blocks(op, pl, hu, hd, cfg, t):
+    """Oracle blocks of (cfg, t) in the plan's kind order, compact form."""
+    return oracle_compact_blocks(op, plan_kind_order(op, pl), hu[cfg, t].astype(np.complex128),
                                  hd[cfg, t].astype(np.complex128))
 
 
-def check_blocks(op, B, hu, hd, ts, cfg=0):
+def check_blocks(op, pl, B, hu, hd, ts, cfg=0):
     for t in ts:
-        ref = oracle_blocks(op, hu, hd, cfg, t)
+        ref = oracle_blocks(op, pl, hu, hd, cfg, t)
         got = B[cfg, t, ..., 0] + 1j * B[cfg, t, ..., 1]
         err = np.max(np.abs(got - ref))
         assert err <= TOL64 * np.max(np.abs(ref)), (t, err, np.max(np.abs(ref)))
@@ -52,7 +53,7 @@ def check_C(op, pl, C, hu, hd, ts, cfg=0, tol=TOL64):
     kidx, coef = pl.table()
     worst = 0.0
     for n, t in enumerate(ts):
-        Bc = oracle_blocks(op, hu, hd, cfg, t)
+        Bc = oracle_blocks(op, pl, hu, hd, cfg, t)
         tab, mag = eval_table(kidx, coef, Bc)
         ref = op.scale * oracle.sum_dp(op, oracle.blocks_raw(op, hu[cfg, t].astype(np.complex128),
                                                               hd[cfg, t].astype(np.complex128)))
@@ -70,7 +71,7 @@ def test_blocks_deuteron_4x4x4x8():
     pl = w.plan_std("2H")
     hu, hd, du, dd = props(1, 1, (4, 4, 4, 8))
     B = w.blocks(pl, du, dd).cpu().numpy()
-    check_blocks(ops.deuteron(), B, hu, hd, range(8))
+    check_blocks(ops.deuteron(), pl, B, hu, hd, range(8))
 
 
 @pytest.mark.parametrize("kernel", ["generic", "rows"])
@@ -81,7 +82,7 @@ def test_blocks_fallback_kernels(monkeypatch, kernel):
     pl = w.plan_std("3He")
     hu, hd, du, dd = props(8, 1, (3, 3, 3, 2))
     B = w.blocks(pl, du, dd).cpu().numpy()
-    check_blocks(ops.helium3(), B, hu, hd, range(2))
+    check_blocks(ops.helium3(), pl, B, hu, hd, range(2))
 
 
 def test_blocks_ragged_volume_and_c64():
@@ -90,7 +91,7 @@ def test_blocks_ragged_volume_and_c64():
     pl = w.plan_std("3He")
     hu, hd, du, dd = props(2, 1, (5, 3, 2, 2), np.complex64)
     B = w.blocks(pl, du, dd).cpu().numpy()
-    check_blocks(ops.helium3(), B, hu, hd, range(2))
+    check_blocks(ops.helium3(), pl, B, hu, hd, range(2))
 
 
 def test_blocks_identity_propagator_closed_form():
@@ -104,7 +105,7 @@ def test_blocks_identity_propagator_closed_form():
     B = w.blocks(pl, S, S).cpu().numpy()
     op = ops.deuteron()
     from tests.helpers import compact
-    for k_plan, k in enumerate(sink_kind_order(op)):
+    for k_plan, k in enumerate(plan_kind_order(op, pl)):
         Wt = np.zeros((12, 12, 12))
         for j1, j2, j3, a, b in op.kinds[k].w:
             Wt[j1, j2, j3] += a
@@ -120,7 +121,7 @@ def test_contract_on_oracle_blocks():
     op = ops.helium3()
     pl = w.plan_std("3He")
     hu, hd, _, _ = props(3, 1, (3, 1, 1, 2))
-    Bc = np.stack([oracle_blocks(op, hu, hd, 0, t) for t in range(2)])[None]
+    Bc = np.stack([oracle_blocks(op, pl, hu, hd, 0, t) for t in range(2)])[None]
     Bd = torch.from_numpy(np.stack([Bc.real, Bc.imag], -1)).contiguous().cuda()
     C = w.contract(pl, Bd).cpu().numpy()
     kidx, coef = pl.table()
@@ -218,7 +219,7 @@ def test_helium3_16cubed_x32_sampled():
     B = w.blocks(pl, du, dd)
     C = w.contract(pl, B).cpu().numpy()
     Bn = B.cpu().numpy()
-    check_blocks(ops.helium3(), Bn, hu, hd, [31])
+    check_blocks(ops.helium3(), pl, Bn, hu, hd, [31])
     check_C(ops.helium3(), pl, C, hu, hd, [0, 31])
 
 
@@ -236,7 +237,7 @@ def test_split_precision_blocks(prec):
     hu, hd, du, dd = props(9, 1, (3, 3, 3, 2))
     B = w.blocks(pl, du, dd, prec).cpu().numpy()
     for t in range(2):
-        ref = oracle_blocks(ops.helium3(), hu, hd, 0, t)
+        ref = oracle_blocks(ops.helium3(), pl, hu, hd, 0, t)
         got = B[0, t, ..., 0] + 1j * B[0, t, ..., 1]
         rel = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
         assert rel <= {"p32": 1e-5, "pb3": 1e-3, "pb6": 1e-5}[prec], (prec, t, rel)
@@ -261,3 +262,27 @@ def test_split_precision_late_time_slices(prec):
     hu, hd, du, dd = props(11, 1, (2, 2, 2, 64))
     C = w.contract(pl, w.blocks(pl, du, dd, prec)).cpu().numpy()
     check_C(ops.deuteron(), pl, C, hu, hd, [40, 63], tol=SPLIT_TOL[prec])
+
+
+# ------------------------------------------------------------------ autotune
+@pytest.mark.parametrize("name,dims,prec", [("2H", (4, 4, 4, 8), "p64"), ("3He", (3, 3, 2, 3), "pb6")])
+def test_autotune_cache_and_parity(tmp_path, name, dims, prec):
+    """The tuner writes its choice to the cache file, a second call with the
+    same shape reads it back without retuning, and every entry point still
+    matches the oracle with the tuned launch shapes."""
+    w = W()
+    pl = w.plan_std(name)
+    path = tmp_path / "tune.txt"
+    w.autotune(pl, dims, "c128", prec, cache_path=path)
+    text = path.read_text()
+    lines = text.splitlines()
+    assert lines[0] == "wick-tune 1"
+    assert any(ln.startswith("blocks ") for ln in lines) and any(ln.startswith("contract ") for ln in lines)
+    w.autotune(pl, dims, "c128", prec, cache_path=path)
+    assert path.read_text() == text
+    hu, hd, du, dd = props(13, 1, dims)
+    tol = TOL64 if prec == "p64" else SPLIT_TOL[prec]
+    C = w.contract(pl, w.blocks(pl, du, dd, prec)).cpu().numpy()
+    check_C(ops.by_name(name), pl, C, hu, hd, range(dims[3]), tol=tol)
+    Cb = w.correlator([pl], [(0, 0)], du, dd, prec).cpu().numpy()
+    check_C(ops.by_name(name), pl, Cb, hu, hd, range(dims[3]), tol=tol)

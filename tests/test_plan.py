@@ -16,7 +16,8 @@ import oracle
 import paper_2411_08962_amd as W
 import wick_inputs as wi
 from oracle import operators as ops
-from tests.helpers import (eval_table, header_symbols, oracle_compact_blocks, sink_kind_order, to_wick)
+from tests.helpers import (eval_table, header_symbols, oracle_compact_blocks, plan_kind_order, sink_kind_order,
+                           to_wick)
 
 
 def small(V=3, wid=901):
@@ -26,7 +27,7 @@ def small(V=3, wid=901):
 
 def check_plan(op, pl, Su, Sd, tol=1e-12):
     kidx, coef = pl.table()
-    Bc = oracle_compact_blocks(op, sink_kind_order(op), Su, Sd)
+    Bc = oracle_compact_blocks(op, plan_kind_order(op, pl), Su, Sd)
     got, mag = eval_table(kidx, coef, Bc)
     ref = op.scale * oracle.sum_dp(op, oracle.blocks_raw(op, Su, Sd))
     assert mag > 0
@@ -60,6 +61,17 @@ def test_std_plan_matches_oracle(name, J):
     check_plan(op, pl, Su, Sd)
 
 
+def test_helium4_full_plan_matches_oracle():
+    # the full 4He operator (2716 patterns, 88M table terms; about a minute of
+    # planning on 8 cores); its kinds are numbered by first use in the built-in
+    # operator's pattern order, which differs from the oracle's
+    op = ops.helium4()
+    pl = W.plan_std("4He")
+    assert plan_kind_order(op, pl) != sink_kind_order(op)
+    assert sorted(plan_kind_order(op, pl)) == list(range(len(op.kinds)))
+    check_plan(op, pl, *small(V=2))
+
+
 @pytest.mark.parametrize("a", [0, 1, 2, 3])
 def test_proton_plan_matches_oracle(a):
     op = ops.proton(a)
@@ -76,8 +88,8 @@ def test_general_plan_equals_std_plan():
     k1, c1 = p1.table()
     k2, c2 = p2.table()
     Su, Sd = small()
-    v1 = eval_table(k1, c1, oracle_compact_blocks(op, sink_kind_order(op), Su, Sd))[0]
-    v2 = eval_table(k2, c2, oracle_compact_blocks(op, sink_kind_order(op), Su, Sd))[0]
+    v1 = eval_table(k1, c1, oracle_compact_blocks(op, plan_kind_order(op, p1), Su, Sd))[0]
+    v2 = eval_table(k2, c2, oracle_compact_blocks(op, plan_kind_order(op, p2), Su, Sd))[0]
     assert abs(v1 - v2) <= 1e-13 * abs(v1)
 
 
@@ -158,7 +170,8 @@ def test_dedup_equals_full_sum_exactly_in_Fp():
     cint = np.round(coef.real).astype(np.int64)
     assert np.all(cint == coef.real)
     rng = np.random.default_rng(2024)
-    order = sink_kind_order(op)
+    order = plan_kind_order(op, pl)
+    assert order == sink_kind_order(op)  # a general plan numbers kinds by first use at the sink
     Bp = _fp_blocks(op, order, rng).reshape(-1)
     table = 0
     for n in range(kidx.shape[1]):
@@ -264,3 +277,24 @@ def test_pauli_operator_gives_empty_table():
     src = [(tuple(i + K for i in p), c) for p, c in op.src]
     pl = W.plan(A=2, kinds=kinds, snk=op.snk, src=src)
     assert pl.n_terms == 0 and pl.stats()["n_groups"] == 0
+
+
+def test_autotune_rejects_bad_arguments_and_corrupt_cache(tmp_path):
+    # argument and cache-file checks come before any device work
+    pl = W.plan_std("2H")
+    with pytest.raises(W.WickError) as e:
+        W.autotune(pl, (4, 0, 4, 8))
+    assert e.value.status == W.EINVAL
+    bad = tmp_path / "tune.txt"
+    bad.write_text("not a tune cache\n")
+    with pytest.raises(W.WickError) as e:
+        W.autotune(pl, (4, 4, 4, 8), cache_path=bad)
+    assert e.value.status == W.ECORRUPT
+    bad.write_text("wick-tune 1\nblocks some:key 256\n")  # a field missing
+    with pytest.raises(W.WickError) as e:
+        W.autotune(pl, (4, 4, 4, 8), cache_path=bad)
+    assert e.value.status == W.ECORRUPT
+    bad.write_text("wick-tune 1\ncontract some:key -5\n")
+    with pytest.raises(W.WickError) as e:
+        W.autotune(pl, (4, 4, 4, 8), cache_path=bad)
+    assert e.value.status == W.ECORRUPT
