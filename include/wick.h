@@ -147,9 +147,15 @@ void wick_plan_destroy(wick_plan_t plan);
 /* ------------------------------------------------------------ GPU compute */
 
 /* Baryon blocks of every kind of the plan on every configuration and time
- * slice: S_u, S_d are device arrays [n_cfg][T][Z][Y][X][12][12] of dtype;
- * dims = {X, Y, Z, T}; B is device double [n_cfg][T][n_kinds][792][2].
- * Sums over sites in a fixed order (deterministic: bitwise repeatable). */
+ * slice (Eq. 2.4): S_u, S_d are device arrays [n_cfg][T][Z][Y][X][12][12]
+ * of dtype (sink index first), 16-byte aligned; dims = {X, Y, Z, T}; B is
+ * device double [n_cfg][T][n_kinds][792][2], entry c = pair(i1, i3)*12 + i2
+ * with pair(i1, i3) = i3(i3-1)/2 + i1, i1 < i3 (the block antisymmetrised in
+ * its two same-flavor slots). Sums over sites in a fixed order
+ * (deterministic: bitwise repeatable). Errors: WICK_EINVAL (null or
+ * misaligned pointers, bad sizes), WICK_EUNSUPPORTED (split precision for
+ * kinds not of nucleon form), WICK_ENOMEM, WICK_EHIP. Asynchronous on
+ * stream; the caller keeps S_u, S_d and B alive until it completes. */
 wick_status wick_blocks(wick_plan_t plan, const void *S_u, const void *S_d, wick_dtype dtype,
                         const int32_t dims[4], int32_t n_cfg, wick_precision prec,
                         wick_stream_t stream, double *B);

@@ -94,9 +94,51 @@ struct DevPlan {
     int split_tiles = 0, split_passes = 0;
     EGroupDev *groups = nullptr;
     BlocksDesc *desc = nullptr;  // null when the staged kernel does not apply
-    uint16_t *kidx = nullptr;
+    uint16_t *kidx = nullptr;  // plain table (null when packed)
     double *coef = nullptr;
+    uint64_t *words = nullptr;  // packed table (null when plain)
+    double2 *pal = nullptr;
+    int n_pal = 0;
 };
+
+TermTable table_of(const DevPlan *d, const wick_plan_s *p)
+{
+    TermTable t{};
+    t.words = d->words;
+    t.pal = d->pal;
+    t.n_pal = d->n_pal;
+    t.coef_real = p->coef_real ? 1 : 0;
+    t.kidx = d->kidx;
+    t.coef = d->coef;
+    return t;
+}
+
+// The packed form of a table (see TermTable), or false when it does not apply.
+bool pack_table(const wick_plan_s *p, std::vector<uint64_t> &words, std::vector<double2> &pal)
+{
+    const size_t nt = (size_t)p->n_terms;
+    if (p->A > 4 || (int)p->kinds.size() > kMaxLdsKinds || nt == 0) return false;
+    words.assign(nt, 0);
+    pal.clear();
+    int last = -1;
+    for (size_t n = 0; n < nt; ++n) {
+        const double re = p->coef_re[n], im = p->coef_im[n];
+        int c = -1;
+        if (last >= 0 && pal[last].x == re && pal[last].y == im) c = last;
+        for (int i = 0; c < 0 && i < (int)pal.size(); ++i)
+            if (pal[i].x == re && pal[i].y == im) c = i;
+        if (c < 0) {
+            if ((int)pal.size() == kMaxPalette) return false;
+            c = (int)pal.size();
+            pal.push_back(double2{re, im});
+        }
+        last = c;
+        uint64_t w = (uint64_t)c << 56;
+        for (int a = 0; a < p->A; ++a) w |= (uint64_t)p->kidx[(size_t)a * nt + n] << (kPackBits * a);
+        words[n] = w;
+    }
+    return true;
+}
 
 std::mutex g_dev_mu;
 std::map<const wick_plan_s *, std::deque<DevPlan>> g_dev;  // deque: stable element addresses
@@ -252,25 +294,39 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
             (which == 0 ? d.nuc_passes : d.split_passes) = nd.n_passes;
         }
     }
-    size_t nt = (size_t)p->n_terms;
-    size_t coef_n = p->coef_real ? nt : 2 * nt;
+    const size_t nt = (size_t)p->n_terms;
+    std::vector<uint64_t> words;
+    std::vector<double2> pal;
+    const bool packed = pack_table(p, words, pal);
+    const size_t coef_n = p->coef_real ? nt : 2 * nt;
+    auto undo = [&] {
+        for (void *q : {(void *)d.groups, (void *)d.desc, (void *)d.nuc, (void *)d.nuc_split, (void *)d.kidx,
+                        (void *)d.coef, (void *)d.words, (void *)d.pal})
+            if (q) (void)hipFree(q);
+    };
     if ((e = hipMalloc(&d.groups, std::max<size_t>(1, hg.size()) * sizeof(EGroupDev))) != hipSuccess ||
-        (e = hipMalloc(&d.kidx, std::max<size_t>(1, nt * p->A) * sizeof(uint16_t))) != hipSuccess ||
-        (e = hipMalloc(&d.coef, std::max<size_t>(1, coef_n) * sizeof(double))) != hipSuccess) {
-        if (d.groups) (void)hipFree(d.groups);
-        if (d.kidx) (void)hipFree(d.kidx);
+        (packed && (e = hipMalloc(&d.words, nt * sizeof(uint64_t))) != hipSuccess) ||
+        (packed && (e = hipMalloc(&d.pal, pal.size() * sizeof(double2))) != hipSuccess) ||
+        (!packed && (e = hipMalloc(&d.kidx, std::max<size_t>(1, nt * p->A) * sizeof(uint16_t))) != hipSuccess) ||
+        (!packed && (e = hipMalloc(&d.coef, std::max<size_t>(1, coef_n) * sizeof(double))) != hipSuccess)) {
+        undo();
         return fail(WICK_ENOMEM, std::string("plan upload hipMalloc: ") + hipGetErrorString(e));
     }
-    std::vector<double> coef(coef_n);
-    for (size_t n = 0; n < nt; ++n) {
+    d.n_pal = (int)pal.size();
+    std::vector<double> coef(packed ? 0 : coef_n);
+    for (size_t n = 0; n < nt && !packed; ++n) {
         if (p->coef_real) coef[n] = p->coef_re[n];
         else { coef[2 * n] = p->coef_re[n]; coef[2 * n + 1] = p->coef_im[n]; }
     }
     // synchronous copies: the host staging vectors die at return
     if ((e = hipMemcpy(d.groups, hg.data(), hg.size() * sizeof(EGroupDev), hipMemcpyHostToDevice)) != hipSuccess ||
-        (nt && (e = hipMemcpy(d.kidx, p->kidx.data(), nt * p->A * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess) ||
-        (nt && (e = hipMemcpy(d.coef, coef.data(), coef_n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess))
+        (packed && (e = hipMemcpy(d.words, words.data(), nt * sizeof(uint64_t), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (packed && (e = hipMemcpy(d.pal, pal.data(), pal.size() * sizeof(double2), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (!packed && nt && (e = hipMemcpy(d.kidx, p->kidx.data(), nt * p->A * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (!packed && nt && (e = hipMemcpy(d.coef, coef.data(), coef_n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)) {
+        undo();
         return hip_fail(e, "plan upload hipMemcpy");
+    }
     (void)s;
     vec.push_back(d);
     *out = &vec.back();
@@ -317,13 +373,19 @@ int64_t tuned_slice(const wick_plan_s *p, int64_t n_ct)
     return it == g_slice.end() ? 0 : it->second;
 }
 
-int64_t default_slice_len(int64_t N, int64_t n_ct)
+// terms per workgroup: about 1024 workgroups over all n_groups (sets of time
+// slices), at least 4096 terms each, a multiple of the workgroup size
+int64_t default_slice_len(int64_t N, int64_t n_groups)
 {
-    // aim for >= 2048 workgroups in total, at least 2048 terms per slice
-    int64_t want_slices = std::max<int64_t>(1, (2048 + n_ct - 1) / n_ct);
-    int64_t len = (N + want_slices - 1) / want_slices;
-    len = std::max<int64_t>(len, 2048);
-    return std::max<int64_t>(1, len);
+    int64_t len = std::max<int64_t>(4096, (N * n_groups + 1023) / 1024);
+    return (len + kCThreads - 1) / kCThreads * kCThreads;
+}
+
+// time slices per term-sum workgroup (0: the blocks do not fit in LDS)
+int slices_per_group(int K, int64_t n_sets)
+{
+    if (K > kMaxLdsKinds) return 0;
+    return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kMaxTG, kMaxLdsKinds / K, n_sets}));
 }
 
 wick_status check_dims(const int32_t dims[4], int32_t n_cfg, int64_t *V)
@@ -346,6 +408,7 @@ wick_status do_blocks(wick_plan_s *p, const void *Su, const void *Sd, int dtype,
     wick_status st = check_dims(dims, n_cfg, &V);
     if (st != WICK_OK) return st;
     if (!Su || !Sd || !B) return fail(WICK_EINVAL, "wick_blocks: null pointer");
+    if (((uintptr_t)Su | (uintptr_t)Sd) & 15) return fail(WICK_EINVAL, "wick_blocks: propagators must be 16-byte aligned");
     if (dtype != WICK_C128 && dtype != WICK_C64) return fail(WICK_EINVAL, "wick_blocks: bad dtype");
     if (prec < WICK_P64 || prec > WICK_PB6) return fail(WICK_EINVAL, "wick_blocks: bad precision");
     DevPlan *dp;
@@ -399,22 +462,22 @@ wick_status do_contract(wick_plan_s *p, const double *B, int n_cfg, int T, hipSt
     if (st != WICK_OK) return st;
     const int64_t n_ct = (int64_t)n_cfg * T;
     if (p->n_terms == 0) {
-        hipError_t e = hipMemsetAsync(C, 0, n_ct * 2 * sizeof(double), s);
-        return e == hipSuccess ? WICK_OK : hip_fail(e, "hipMemsetAsync");
+        hipError_t e = launch_zero(C, n_ct * 2, s);
+        return e == hipSuccess ? WICK_OK : hip_fail(e, "wick_contract zero fill");
     }
     ContractLaunch L{};
     L.B = B;
-    L.kidx = dp->kidx;
-    L.coef = dp->coef;
-    L.coef_real = p->coef_real;
+    L.tab = table_of(dp, p);
     L.A = p->A;
     L.K = (int)p->kinds.size();
     L.N = p->n_terms;
     L.n_ct = (int)n_ct;
+    L.tg = slices_per_group(L.K, n_ct);
+    const int64_t n_groups = L.tg ? (n_ct + L.tg - 1) / L.tg : n_ct;
     const int64_t sl = slice_override > 0 ? slice_override : tuned_slice(p, n_ct);
-    L.slice_len = sl > 0 ? sl : default_slice_len(L.N, n_ct);
+    L.slice_len = sl > 0 ? sl : default_slice_len(L.N, n_groups);
     L.n_slices = (int)((L.N + L.slice_len - 1) / L.slice_len);
-    if ((int64_t)L.n_slices * n_ct > 0x7ffffff0LL) return fail(WICK_ETOOBIG, "wick_contract: grid too large");
+    if ((int64_t)L.n_slices * n_groups > 0x7ffffff0LL) return fail(WICK_ETOOBIG, "wick_contract: grid too large");
     void *ws;
     if ((st = workspace(s, (size_t)n_ct * L.n_slices * 16, &ws)) != WICK_OK) return st;
     L.partial = (double *)ws;
@@ -508,7 +571,7 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
     std::vector<int64_t> bout(n_items + 1, 0);
     std::vector<BatchContractItem> ci(n_items);
     std::vector<BatchContractWork> cw;
-    int nt_max = 0, max_K = 0, passes_max = 1;
+    int nt_max = 0, passes_max = 1;
     std::vector<DevPlan *> dps(n_items);
     for (int i = 0; i < n_items; ++i) {
         wick_plan_s *p = plans[items[i].plan];
@@ -519,7 +582,6 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
         if (!nd) return fail(WICK_EUNSUPPORTED, "batched path needs kinds of nucleon form");
         nt_max = std::max(nt_max, prec == WICK_P64 ? dp->nuc_tiles : dp->split_tiles);
         passes_max = std::max(passes_max, prec == WICK_P64 ? dp->nuc_passes : dp->split_passes);
-        max_K = std::max(max_K, (int)p->kinds.size());
     }
     // sites per chunk: enough workgroups to fill the chip, at least 64 sites each
     int64_t want_chunks = std::max<int64_t>(1, (2048 + (int64_t)n_items * T * passes_max - 1) /
@@ -529,7 +591,18 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
     chunk_sites = (chunk_sites + 7) / 8 * 8;
     const int n_chunks = (int)((V + chunk_sites - 1) / chunk_sites);
     int64_t part = 0, bo = 0, cpart = 0;
-    const int64_t want_slices = std::max<int64_t>(1, (4096 + (int64_t)n_items * T - 1) / ((int64_t)n_items * T));
+    // term sum: terms per workgroup from the whole batch's work (about 2048 workgroups)
+    int64_t total = 0;
+    size_t clds = 0;
+    for (int i = 0; i < n_items; ++i) {
+        const wick_plan_s *p = plans[items[i].plan];
+        const int tg = slices_per_group((int)p->kinds.size(), T);
+        if (tg == 0) return fail(WICK_EUNSUPPORTED, "batch: a plan with more than 12 kinds");
+        total += p->n_terms * ((T + tg - 1) / tg);
+        clds = std::max(clds, contract_tg_lds_bytes((int)p->kinds.size(), tg));
+    }
+    int64_t S = std::max<int64_t>(4096, (total + 2047) / 2048);
+    S = (S + kCThreads - 1) / kCThreads * kCThreads;
     for (int i = 0; i < n_items; ++i) {
         wick_plan_s *p = plans[items[i].plan];
         DevPlan *dp = dps[i];
@@ -548,19 +621,18 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
             for (int ch = 0; ch < n_chunks; ++ch)
                 for (int ps = 0; ps < passes; ++ps) bw.push_back({i, t, ch, ps});
         BatchContractItem &c = ci[i];
-        c.kidx = dp->kidx;
-        c.coef = dp->coef;
+        c.tab = table_of(dp, p);
         c.N = p->n_terms;
-        c.slice_len = std::max<int64_t>(2048, (c.N + want_slices - 1) / want_slices);
-        c.n_slices = (int)std::max<int64_t>(1, (c.N + c.slice_len - 1) / c.slice_len);
+        c.slice_len = S;
+        c.n_slices = (int)std::max<int64_t>(1, (c.N + S - 1) / S);
         c.b_off = bi[i].b_off;
         c.part_off = cpart;
         c.A = p->A;
         c.K = K;
-        c.coef_real = p->coef_real ? 1 : 0;
+        c.tg = slices_per_group(K, T);
         cpart += (int64_t)T * c.n_slices;
-        for (int t = 0; t < T; ++t)
-            for (int sl = 0; sl < c.n_slices; ++sl) cw.push_back({i, t, sl, 0});
+        for (int t0 = 0; t0 < T; t0 += c.tg)
+            for (int sl = 0; sl < c.n_slices; ++sl) cw.push_back({i, t0, sl, std::min(c.tg, T - t0)});
     }
     bout[n_items] = bo;
     if (bw.size() > 0x7ffffff0ULL || cw.size() > 0x7ffffff0ULL) return fail(WICK_ETOOBIG, "batch too large");
@@ -592,12 +664,11 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
     L.citems = b.citems;
     L.cwork = b.cwork;
     L.n_cwork = (int)cw.size();
-    L.max_K = max_K;
+    L.contract_lds = clds;
     L.partial = (double *)b.partial;
     L.B = (double *)b.B;
     L.cpartial = (double *)b.cpartial;
     L.C = C;
-    if (contract_lds_bytes(max_K) > 160 * 1024 - 256) return fail(WICK_EUNSUPPORTED, "batch: more than 12 kinds");
     return WICK_OK;
 }
 // ------------------------------------------------------------- autotuning
@@ -827,6 +898,8 @@ void release_device_tables(wick_plan_s *p)
         (void)hipFree(d.nuc_split);
         (void)hipFree(d.kidx);
         (void)hipFree(d.coef);
+        (void)hipFree(d.words);
+        (void)hipFree(d.pal);
     }
     (void)hipSetDevice(cur);
     g_dev.erase(it);
@@ -944,6 +1017,8 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
 {
     if (!plans || n_plans < 1 || !items || n_items < 1 || !C || !S_u || !S_d)
         return fail(WICK_EINVAL, "wick_correlator: bad plans / items / pointers");
+    if (((uintptr_t)S_u | (uintptr_t)S_d) & 15)
+        return fail(WICK_EINVAL, "wick_correlator: propagators must be 16-byte aligned");
     int64_t V;
     wick_status st = check_dims(dims, n_cfg, &V);
     if (st != WICK_OK) return st;

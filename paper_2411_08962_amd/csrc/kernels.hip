@@ -311,6 +311,26 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_f64_staged_kernel(
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
+// One wave-wide 16-byte-per-lane load from global memory straight into LDS:
+// lane i's 16 bytes land at lds_dst + 16 i (lds_dst wave-uniform). Written as
+// inline assembly so that the compiler's wait-count insertion, which cannot
+// tell the two staging buffers apart, does not make every LDS read of the
+// batch in use wait for the loads of the next one; the kernel waits for them
+// itself (vmcnt) before the barrier that publishes the buffer.
+__device__ __forceinline__ void lds_dma16(const void *src, void *lds_dst)
+{
+    const uint32_t l = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) void *)lds_dst;
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(l) : "memory");
+}
+
+typedef const __attribute__((address_space(4))) NucDesc CNucDesc;
+typedef const __attribute__((address_space(4))) NucGroupDev CNucGroup;
+
+constexpr int kNucWaves = 12;                   // 3 column tiles x 4 site phases
+constexpr int kNucThreads = 64 * kNucWaves;
+constexpr int kNucSites = 16;                   // sites per staged batch: one quad per phase
+constexpr int kNucColGroups = kNTiles / 3;      // workgroups per work unit (column tiles 3j .. 3j+2)
+
 __device__ __forceinline__ void split2(double x, __bf16 &h, __bf16 &l)
 {
     h = (__bf16)(float)x;
@@ -325,25 +345,30 @@ __device__ __forceinline__ void split3(double x, __bf16 &h, __bf16 &m, __bf16 &l
 }
 
 template <typename TIn, int NT, int MODE>
-__global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_kernel(
+__global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
     const TIn *__restrict__ Su, const TIn *__restrict__ Sd, const NucDesc *__restrict__ desc_one, int64_t V,
     int chunk_sites, int n_chunks_one, int K_one, int n_work, double2 *__restrict__ partial,
     const BatchBlockItem *__restrict__ bitems, const BatchBlockWork *__restrict__ bwork, int T)
 {
     constexpr bool kSplit = MODE != WICK_P64;
-    __shared__ double2 sbuf[2][kSB][2][144];
-    __shared__ double smax[kNTiles];
-    const int lb = xcd_block();
-    if (lb >= n_work) return;
+    // two staging buffers [flavor][site][144] as distinct LDS variables, so the
+    // compiler can tell the reads of one from the loads into the other
+    __shared__ __attribute__((aligned(16))) TIn sbuf0[2][kNucSites][144];
+    __shared__ __attribute__((aligned(16))) TIn sbuf1[2][kNucSites][144];
+    __shared__ double smax[kNucWaves];
+    const int lbw = xcd_block();
+    if (lbw >= n_work * kNucColGroups) return;
+    // the kNucColGroups workgroups of one work unit are adjacent (one XCD, shared L2)
+    const int lb = lbw / kNucColGroups, jg = lbw % kNucColGroups;
     // one plan: the workgroup's (cfg*T + t, chunk, pass) follow from its id;
     // a batch: from its work entry and its item's descriptor
-    const NucDesc *desc;
+    const NucDesc *desc_ptr;
     int pass, chunk, n_chunks, K;
     int64_t s_off, p_off;
     if (bwork) {
         const BatchBlockWork w = bwork[lb];
         const BatchBlockItem &it = bitems[w.item];
-        desc = it.desc;
+        desc_ptr = it.desc;
         pass = w.pass;
         chunk = w.chunk;
         n_chunks = it.n_chunks;
@@ -351,20 +376,24 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_kernel(
         s_off = it.s_off + (int64_t)w.t * V * 144;
         p_off = it.part_off + ((int64_t)w.t * n_chunks + chunk) * K * 1728;
     } else {
-        desc = desc_one;
+        desc_ptr = desc_one;
         n_chunks = n_chunks_one;
         K = K_one;
-        pass = lb % desc->n_passes;
-        chunk = (lb / desc->n_passes) % n_chunks;
-        const int64_t ct = lb / desc->n_passes / n_chunks;
+        pass = lb % desc_one->n_passes;
+        chunk = (lb / desc_one->n_passes) % n_chunks;
+        const int64_t ct = lb / desc_one->n_passes / n_chunks;
         s_off = ct * V * 144;
         p_off = (ct * n_chunks + chunk) * (int64_t)K * 1728;
     }
-    const int nt = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the descriptor is read through the constant address space: uniform scalar
+    // loads (counted apart from the propagator loads in flight)
+    const CNucDesc *desc = (const CNucDesc *)desc_ptr;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ph = wv / 3, nt = 3 * jg + wv % 3;  // site phase, column tile
     const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
     const int n = nt * 16 + c, i2 = n / 12, i3 = n % 12;
     const int npg = desc->pass_ngroups[pass];
-    const int32_t *tgroup = desc->tile_group[pass];
+    const __attribute__((address_space(4))) int32_t *tgroup = desc->tile_group[pass];
 
     // per tile: offset of this lane's Aop column inside a site's S_f (row 3*alpha, column i1);
     // padded columns (kind index past the group) read a valid entry and are never stored
@@ -374,7 +403,7 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_kernel(
         const int g = tgroup[t];
         bo[t] = 0;
         if (g >= 0) {
-            const NucGroupDev &G = desc->groups[g];
+            const CNucGroup &G = desc->groups[g];
             const int m = desc->tile_mt[pass][t] * 16 + c;
             const int kk = m / 12 < G.nk ? m / 12 : G.nk - 1;
             bo[t] = 36 * G.alpha[kk] + m % 12;
@@ -386,72 +415,88 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_kernel(
 
     const int64_t x0 = (int64_t)chunk * chunk_sites;
     const int64_t x1 = x0 + chunk_sites < V ? x0 + chunk_sites : V;
-    const int nb = (int)((x1 - x0 + kSB - 1) / kSB);
-    const TIn *base[2] = {Su + s_off, Sd + s_off};
-    constexpr int kPer = kSB * 2 * 144 / kStagedThreads;
-    double2 stage[kPer];
-    auto load = [&](int b) {
+    const int nb = (int)((x1 - x0 + kNucSites - 1) / kNucSites);
+    const TIn *const bu = Su + s_off, *const bd = Sd + s_off;
+    // Staging of batch b into buffer buf, layout [flavor][site][144]. A full
+    // batch goes from global memory straight to LDS (16 bytes per lane, no
+    // registers): each wave-wide load covers 64 lanes x 16 bytes inside one
+    // flavor, contiguous in global memory and in LDS. The ragged last batch
+    // of a chunk goes through registers with zeros past the end (E = 0 there).
+    constexpr int kFlavorEnt = kNucSites * 144;
+    constexpr int kEntries = 2 * kFlavorEnt;
+    constexpr int kLaneEnt = 16 / (int)sizeof(TIn);                // entries per lane and load
+    constexpr int kWaveEnt = 64 * kLaneEnt;
+    constexpr int kLoads = kEntries / (kNucThreads * kLaneEnt);    // loads per lane and batch
+    static_assert(kEntries % (kNucThreads * kLaneEnt) == 0 && kFlavorEnt % kWaveEnt == 0,
+                  "wave loads must tile the batch without crossing a flavor");
+    auto issue = [&](int b, TIn *dst0) {
+        const int64_t xb = x0 + (int64_t)b * kNucSites;
+        if (xb + kNucSites <= x1) {
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = threadIdx.x + u * kStagedThreads;     // [site][flavor][144]
-            const int s = e / 288, fl = (e / 144) & 1, j = e % 144;
-            const int64_t x = x0 + (int64_t)b * kSB + s;
-            if (x < x1) {
-                const TIn v = base[fl][x * 144 + j];
-                stage[u] = double2{(double)v.x, (double)v.y};
-            } else {
-                stage[u] = double2{0.0, 0.0};
+            for (int u = 0; u < kLoads; ++u) {
+                const int e0 = (u * kNucWaves + wv) * kWaveEnt;  // wave-uniform first entry
+                const int fl = e0 / kFlavorEnt;
+                const TIn *src = (fl ? bd : bu) + xb * 144 + (e0 - fl * kFlavorEnt) + lane * kLaneEnt;
+                lds_dma16(src, dst0 + e0);
+            }
+        } else {
+            for (int e = threadIdx.x; e < kEntries; e += kNucThreads) {
+                const int fl = e / kFlavorEnt, st = (e % kFlavorEnt) / 144, j = e % 144;
+                TIn v{};
+                if (xb + st < x1) v = (fl ? bd : bu)[(xb + st) * 144 + j];
+                dst0[e] = v;
             }
         }
     };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) (&sbuf[buf][0][0][0])[threadIdx.x + u * kStagedThreads] = stage[u];
+    auto wait_staged = [] { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); };
+    auto rd = [](const TIn *p) {
+        const TIn v = *p;
+        return double2{(double)v.x, (double)v.y};
     };
-    load(0);
+    issue(0, &sbuf0[0][0][0]);
+    wait_staged();
+    __syncthreads();
     // split modes: operand scales 2^-2e (E) and 2^-e (Aop), from the first batch
     double scE = 1.0, scA = 1.0, unscale = 1.0;
     if constexpr (kSplit) {
         double mx = 0.0;
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) mx = fmax(mx, fmax(fabs(stage[u].x), fabs(stage[u].y)));
+        for (int e = threadIdx.x; e < kEntries; e += kNucThreads) {
+            const double2 v = rd(&sbuf0[0][0][0] + e);
+            mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+        }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-        if (lane == 0) smax[nt] = mx;
+        if (lane == 0) smax[wv] = mx;
         __syncthreads();
         mx = 0.0;
 #pragma unroll
-        for (int w = 0; w < kNTiles; ++w) mx = fmax(mx, smax[w]);
+        for (int w = 0; w < kNucWaves; ++w) mx = fmax(mx, smax[w]);
         const int e = mx > 0.0 ? ilogb(mx) : 0;
         scA = ldexp(1.0, -e);
         scE = ldexp(1.0, -2 * e);
         unscale = ldexp(1.0, 3 * e);
     }
-    store(0);
-    __syncthreads();
-    for (int b = 0; b < nb; ++b) {
-        const int cur = b & 1;
-        if (b + 1 < nb) load(b + 1);
+    // one staged batch: this wave's site quad against every group of the pass
+    auto batch = [&](const TIn (*buf)[kNucSites][144]) {
         f4 acc32[NT][2];
         if constexpr (kSplit) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc32[t][0] = acc32[t][1] = f4{0, 0, 0, 0};
         }
-#pragma unroll 1
-        for (int st = 0; st < kSB / 4; ++st) {
-            const int s = st * 4 + q;   // sites past the end are zeros in LDS: E = 0
+        {
+            const int s = 4 * ph + q;   // this wave's site quad; sites past the end are zeros in LDS: E = 0
 #pragma unroll 1
             for (int gl = 0; gl < npg; ++gl) {
                 const int g = desc->pass_groups[pass][gl];
-                const NucGroupDev &G = desc->groups[g];
-                const double2 *sfb = sbuf[cur][s][G.f];
-                const double2 *sgb = sbuf[cur][s][G.g];
+                const CNucGroup &G = desc->groups[g];
+                const TIn *sfb = buf[G.f][s];
+                const TIn *sgb = buf[G.g][s];
                 double e0x = 0, e0y = 0, e1x = 0, e1y = 0, e2x = 0, e2y = 0;
                 for (int p = 0; p < G.npair; ++p) {
-                    const double2 *pa = sgb + 36 * G.s2[p] + i2;
-                    const double2 *pb = sfb + 36 * G.s3[p] + i3;
-                    const double2 a0 = pa[0], a1 = pa[12], a2 = pa[24];
-                    const double2 b0 = pb[0], b1 = pb[12], b2 = pb[24];
+                    const TIn *pa = sgb + 36 * G.s2[p] + i2;
+                    const TIn *pb = sfb + 36 * G.s3[p] + i3;
+                    const double2 a0 = rd(pa), a1 = rd(pa + 12), a2 = rd(pa + 24);
+                    const double2 b0 = rd(pb), b1 = rd(pb + 12), b2 = rd(pb + 24);
                     const double m = (double)G.m[p];
                     // E_r = M * sum eps[r][c3][c2] a_c2 b_c3
                     e0x += m * ((a2.x * b1.x - a2.y * b1.y) - (a1.x * b2.x - a1.y * b2.y));
@@ -466,20 +511,15 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_kernel(
                     const double ex = r == 0 ? e0x : (r == 1 ? e1x : e2x);
                     const double ey = r == 0 ? e0y : (r == 1 ? e1y : e2y);
                     if constexpr (MODE == WICK_P64) {
-                        double2 v[NT];
-#pragma unroll
-                        for (int t = 0; t < NT; ++t) {
-                            if (tgroup[t] != g) continue;
-                            v[t] = sfb[bo[t] + 12 * r];
-                            acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, v[t].x, acc[t][0], 0, 0, 0);
-                            acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, v[t].y, acc[t][1], 0, 0, 0);
-                        }
                         const double ney = -ey;
 #pragma unroll
                         for (int t = 0; t < NT; ++t) {
                             if (tgroup[t] != g) continue;
-                            acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ney, v[t].y, acc[t][0], 0, 0, 0);
-                            acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey, v[t].x, acc[t][1], 0, 0, 0);
+                            const double2 v = rd(sfb + bo[t] + 12 * r);
+                            acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, v.x, acc[t][0], 0, 0, 0);
+                            acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, v.y, acc[t][1], 0, 0, 0);
+                            acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ney, v.y, acc[t][0], 0, 0, 0);
+                            acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey, v.x, acc[t][1], 0, 0, 0);
                         }
                     } else if constexpr (MODE == WICK_P32) {
                         const float fx = (float)(ex * scE), fy = (float)(ey * scE);
@@ -487,7 +527,7 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_kernel(
 #pragma unroll
                         for (int t = 0; t < NT; ++t) {
                             if (tgroup[t] != g) continue;
-                            const double2 d = sfb[bo[t] + 12 * r];
+                            const double2 d = rd(sfb + bo[t] + 12 * r);
                             v[t] = float2{(float)(d.x * scA), (float)(d.y * scA)};
                             acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fx, v[t].x, acc32[t][0], 0, 0, 0);
                             acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fx, v[t].y, acc32[t][1], 0, 0, 0);
@@ -507,7 +547,7 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_kernel(
 #pragma unroll
                         for (int t = 0; t < NT; ++t) {
                             if (tgroup[t] != g) continue;
-                            const double2 d = sfb[bo[t] + 12 * r];
+                            const double2 d = rd(sfb + bo[t] + 12 * r);
                             __bf16 axh, axl, ayh, ayl;
                             split2(d.x * scA, axh, axl);
                             split2(d.y * scA, ayh, ayl);
@@ -526,7 +566,7 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_kernel(
 #pragma unroll
                         for (int t = 0; t < NT; ++t) {
                             if (tgroup[t] != g) continue;
-                            const double2 d = sfb[bo[t] + 12 * r];
+                            const double2 d = rd(sfb + bo[t] + 12 * r);
                             __bf16 ah, am, al, bh, bm, bl;
                             split3(d.x * scA, ah, am, al);
                             split3(d.y * scA, bh, bm, bl);
@@ -552,14 +592,52 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_nucleon_kernel(
                     acc[t][1][v] += (double)acc32[t][1][v] * unscale;
                 }
         }
-        if (b + 1 < nb) store(cur ^ 1);
+    };
+    for (int b = 0; b < nb; b += 2) {
+        if (b + 1 < nb) issue(b + 1, &sbuf1[0][0][0]);
+        batch(sbuf0);
+        wait_staged();
+        __syncthreads();
+        if (b + 1 >= nb) break;
+        if (b + 2 < nb) issue(b + 2, &sbuf0[0][0][0]);
+        batch(sbuf1);
+        wait_staged();
         __syncthreads();
     }
+    // sum the four site phases in a fixed order through LDS (the staging
+    // buffers are free now): ((phase 3 + phase 2) + phase 1) + phase 0
+    constexpr int kSlot = NT * 4 * 64;  // double2 per wave; slots 0, 1 in buffer 0, slot 2 in buffer 1
+    static_assert(2 * kSlot * sizeof(double2) <= sizeof(sbuf0) && kSlot * sizeof(double2) <= sizeof(sbuf1),
+                  "reduction slots must fit the staging buffers");
+    const int a3 = wv % 3;
+    double2 *slot = (a3 < 2 ? reinterpret_cast<double2 *>(&sbuf0[0][0][0]) + a3 * kSlot
+                            : reinterpret_cast<double2 *>(&sbuf1[0][0][0])) + lane;
+    for (int src = 3; src >= 1; --src) {
+        if (ph == src) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) slot[(t * 4 + v) * 64] = double2{acc[t][0][v], acc[t][1][v]};
+        }
+        __syncthreads();
+        if (ph == src - 1) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double2 o = slot[(t * 4 + v) * 64];
+                    acc[t][0][v] += o.x;
+                    acc[t][1][v] += o.y;
+                }
+        }
+        __syncthreads();
+    }
+    if (ph != 0) return;
     double2 *P = partial + p_off;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         if (tgroup[t] < 0) continue;
-        const NucGroupDev &G = desc->groups[tgroup[t]];
+        const CNucGroup &G = desc->groups[tgroup[t]];
         const int m = desc->tile_mt[pass][t] * 16 + c, kk = m / 12, i1 = m % 12;
         if (kk >= G.nk) continue;
         double2 *row = P + ((int64_t)G.kind_out[kk] * 12 + i1) * 144 + nt * 16;
@@ -597,23 +675,17 @@ __global__ __launch_bounds__(256) void blocks_reduce_kernel(const double2 *__res
     B[idx] = double2{sx, sy};
 }
 
-template <int A, bool REAL, bool LDSB>
+template <int A, bool REAL>
 __global__ __launch_bounds__(256) void contract_kernel(const double2 *__restrict__ B, const uint16_t *__restrict__ kidx,
                                                        const double *__restrict__ coef, int64_t N, int K, int n_ct,
                                                        int n_slices, int64_t slice_len, double2 *__restrict__ partial)
 {
-    extern __shared__ double2 sB[];
     __shared__ double red[2][4];
     const int lb = xcd_block();
     if (lb >= n_ct * n_slices) return;
     const int ct = lb / n_slices, slice = lb % n_slices;
     const double2 *Bc = B + (int64_t)ct * K * 792;
     const double2 *src = Bc;
-    if (LDSB) {
-        for (int i = threadIdx.x; i < K * 792; i += blockDim.x) sB[i] = Bc[i];
-        __syncthreads();
-        src = sB;
-    }
     const int64_t n0 = (int64_t)slice * slice_len;
     const int64_t n1 = n0 + slice_len < N ? n0 + slice_len : N;
     double ar = 0.0, ai = 0.0;
@@ -653,6 +725,124 @@ __global__ __launch_bounds__(256) void contract_kernel(const double2 *__restrict
         }
         partial[(int64_t)ct * n_slices + slice] = double2{sr, si};
     }
+}
+
+// Term sum with the blocks of ntg <= kMaxTG consecutive time slices in LDS:
+// each term's word (or plain indices and coefficient) is read once and
+// evaluated for every staged slice.
+template <int A, bool PACKED>
+__device__ __forceinline__ void term_sum(const double2 *__restrict__ sB, int KB, int ntg,
+                                         const double2 *__restrict__ spal, const TermTable &tab, int64_t N,
+                                         int64_t n0, int64_t n1, double (&ar)[kMaxTG], double (&ai)[kMaxTG])
+{
+    for (int64_t n = n0 + threadIdx.x; n < n1; n += kCThreads) {
+        int idx[A];
+        double cx, cy;
+        if constexpr (PACKED) {
+            const uint64_t w = tab.words[n];
+#pragma unroll
+            for (int a = 0; a < A; ++a) idx[a] = (int)(w >> (kPackBits * a)) & ((1 << kPackBits) - 1);
+            const double2 c = spal[(int)(w >> 56)];
+            cx = c.x;
+            cy = c.y;
+        } else {
+#pragma unroll
+            for (int a = 0; a < A; ++a) idx[a] = tab.kidx[(int64_t)a * N + n];
+            if (tab.coef_real) {
+                cx = tab.coef[n];
+                cy = 0.0;
+            } else {
+                cx = tab.coef[2 * n];
+                cy = tab.coef[2 * n + 1];
+            }
+        }
+#pragma unroll
+        for (int tg = 0; tg < kMaxTG; ++tg) {
+            if (tg < ntg) {
+                const double2 *Bt = sB + tg * KB;
+                double2 p = Bt[idx[0]];
+#pragma unroll
+                for (int a = 1; a < A; ++a) {
+                    const double2 b = Bt[idx[a]];
+                    p = double2{p.x * b.x - p.y * b.y, p.x * b.y + p.y * b.x};
+                }
+                ar[tg] += cx * p.x - cy * p.y;
+                ai[tg] += cx * p.y + cy * p.x;
+            }
+        }
+    }
+}
+
+// Stage ntg slices of K blocks (contiguous in B) and the palette.
+__device__ __forceinline__ void stage_blocks(const double2 *__restrict__ Bsrc, int n, const TermTable &tab,
+                                             double2 *__restrict__ sB, double2 *__restrict__ spal)
+{
+    for (int i = threadIdx.x; i < n; i += kCThreads) sB[i] = Bsrc[i];
+    if (tab.words)
+        for (int i = threadIdx.x; i < tab.n_pal; i += kCThreads) spal[i] = tab.pal[i];
+    __syncthreads();
+}
+
+// Workgroup sum of each slice's accumulators in a fixed order; out[tg * stride].
+__device__ __forceinline__ void reduce_tg(double (&ar)[kMaxTG], double (&ai)[kMaxTG], int ntg,
+                                          double (*red)[2][kCThreads / 64], double2 *__restrict__ out,
+                                          int64_t stride)
+{
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int tg = 0; tg < kMaxTG; ++tg) {
+        if (tg < ntg) {
+            double x = ar[tg], y = ai[tg];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                x += __shfl_xor(x, off);
+                y += __shfl_xor(y, off);
+            }
+            if ((threadIdx.x & 63) == 0) {
+                red[tg][0][w] = x;
+                red[tg][1][w] = y;
+            }
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ntg) {
+        const int tg = threadIdx.x;
+        double sr = 0.0, si = 0.0;
+        for (int i = 0; i < kCThreads / 64; ++i) {
+            sr += red[tg][0][i];
+            si += red[tg][1][i];
+        }
+        out[tg * stride] = double2{sr, si};
+    }
+}
+
+// One plan: workgroup (group of tg consecutive (cfg, t) sets, table slice).
+template <int A, bool PACKED>
+__global__ __launch_bounds__(kCThreads) void contract_tg_kernel(const double2 *__restrict__ B, TermTable tab,
+                                                                int64_t N, int K, int n_ct, int tg, int n_slices,
+                                                                int64_t slice_len, double2 *__restrict__ partial)
+{
+    extern __shared__ double2 lds[];
+    __shared__ double red[kMaxTG][2][kCThreads / 64];
+    const int n_groups = (n_ct + tg - 1) / tg;
+    const int lb = xcd_block();
+    if (lb >= n_groups * n_slices) return;
+    const int g = lb / n_slices, slice = lb % n_slices;
+    const int ct0 = g * tg, ntg = n_ct - ct0 < tg ? n_ct - ct0 : tg;
+    const int KB = K * 792;
+    double2 *spal = lds, *sB = lds + kMaxPalette;
+    stage_blocks(B + (int64_t)ct0 * KB, ntg * KB, tab, sB, spal);
+    const int64_t n0 = (int64_t)slice * slice_len;
+    const int64_t n1 = n0 + slice_len < N ? n0 + slice_len : N;
+    double ar[kMaxTG] = {}, ai[kMaxTG] = {};
+    term_sum<A, PACKED>(sB, KB, ntg, spal, tab, N, n0, n1, ar, ai);
+    reduce_tg(ar, ai, ntg, red, partial + (int64_t)ct0 * n_slices + slice, n_slices);
+}
+
+__global__ void zero_kernel(double *__restrict__ p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
 }
 
 __global__ void contract_finalize_kernel(const double2 *__restrict__ partial, int n_ct, int n_slices,
@@ -706,62 +896,40 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(const double2 *__rest
     B[idx] = double2{sx, sy};
 }
 
-// Term sum of a batch: one workgroup per (item, t, slice) work entry; A, the
-// number of kinds and the coefficient type are read from the item.
-__global__ __launch_bounds__(256) void contract_batch_kernel(const double2 *__restrict__ B,
-                                                             const BatchContractItem *__restrict__ items,
-                                                             const BatchContractWork *__restrict__ work, int n_work,
-                                                             double2 *__restrict__ partial)
+// Term sum of a batch: one workgroup per (item, first time slice, table
+// slice) work entry; A, the number of kinds, the slices per workgroup and
+// the table form are read from the item.
+__global__ __launch_bounds__(kCThreads) void contract_batch_kernel(const double2 *__restrict__ B,
+                                                                   const BatchContractItem *__restrict__ items,
+                                                                   const BatchContractWork *__restrict__ work,
+                                                                   int n_work, double2 *__restrict__ partial)
 {
-    extern __shared__ double2 sB[];
-    __shared__ double red[2][4];
+    extern __shared__ double2 lds[];
+    __shared__ double red[kMaxTG][2][kCThreads / 64];
     const int lb = xcd_block();
     if (lb >= n_work) return;
     const BatchContractWork w = work[lb];
     const BatchContractItem &it = items[w.item];
-    const int A = it.A, K = it.K;
-    const double2 *Bc = B + it.b_off + (int64_t)w.t * K * 792;
-    for (int i = threadIdx.x; i < K * 792; i += blockDim.x) sB[i] = Bc[i];
-    __syncthreads();
-    const int64_t N = it.N;
+    const int KB = it.K * 792, ntg = w.ntg;
+    double2 *spal = lds, *sB = lds + kMaxPalette;
+    stage_blocks(B + it.b_off + (int64_t)w.t0 * KB, ntg * KB, it.tab, sB, spal);
     const int64_t n0 = (int64_t)w.slice * it.slice_len;
-    const int64_t n1 = n0 + it.slice_len < N ? n0 + it.slice_len : N;
-    double ar = 0.0, ai = 0.0;
-    for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
-        double2 p = sB[it.kidx[n]];
-        for (int a = 1; a < A; ++a) {
-            const double2 b = sB[it.kidx[(int64_t)a * N + n]];
-            p = double2{p.x * b.x - p.y * b.y, p.x * b.y + p.y * b.x};
-        }
-        if (it.coef_real) {
-            const double cr = it.coef[n];
-            ar += cr * p.x;
-            ai += cr * p.y;
-        } else {
-            const double cr = it.coef[2 * n], ci = it.coef[2 * n + 1];
-            ar += cr * p.x - ci * p.y;
-            ai += cr * p.y + ci * p.x;
-        }
+    const int64_t n1 = n0 + it.slice_len < it.N ? n0 + it.slice_len : it.N;
+    double ar[kMaxTG] = {}, ai[kMaxTG] = {};
+    const bool packed = it.tab.words != nullptr;
+    switch (it.A * 2 + (packed ? 1 : 0)) {
+    case 2: term_sum<1, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 3: term_sum<1, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 4: term_sum<2, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 5: term_sum<2, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 6: term_sum<3, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 7: term_sum<3, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 8: term_sum<4, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 9: term_sum<4, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 10: term_sum<5, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    default: break;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        ar += __shfl_xor(ar, off);
-        ai += __shfl_xor(ai, off);
-    }
-    const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red[0][wv] = ar;
-        red[1][wv] = ai;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double sr = 0.0, si = 0.0;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
-            sr += red[0][i];
-            si += red[1][i];
-        }
-        partial[it.part_off + (int64_t)w.t * it.n_slices + w.slice] = double2{sr, si};
-    }
+    reduce_tg(ar, ai, ntg, red, partial + it.part_off + (int64_t)w.t0 * it.n_slices + w.slice, it.n_slices);
 }
 
 __global__ void batch_finalize_kernel(const double2 *__restrict__ partial,
@@ -792,17 +960,17 @@ hipError_t launch_blocks(const BlockLaunch &L, hipStream_t s)
     Probe pr("blocks", s);
     if (L.nuc) {
         const int64_t work = n_ct * L.n_chunks * L.nuc_passes;
-        if (work > 0x7ffffff0LL) return hipErrorInvalidValue;
-        const unsigned blocks = (unsigned)round8(work);
+        if (work * kNucColGroups > 0x7ffffff0LL) return hipErrorInvalidValue;
+        const unsigned blocks = (unsigned)round8(work * kNucColGroups);
         bool done = false;
 #define WICK_NUC(NTV, MODE)                                                                                       \
     if (L.nuc_tiles == NTV && L.prec == MODE) {                                                                   \
         if (L.dtype == 0)                                                                                         \
-            hipLaunchKernelGGL((blocks_nucleon_kernel<double2, NTV, MODE>), dim3(blocks), dim3(kStagedThreads), 0, \
+            hipLaunchKernelGGL((blocks_nucleon_kernel<double2, NTV, MODE>), dim3(blocks), dim3(kNucThreads), 0,    \
                                s, (const double2 *)L.Su, (const double2 *)L.Sd, L.nuc, L.V, L.chunk_sites,         \
                                L.n_chunks, L.K, (int)work, (double2 *)L.partial, nullptr, nullptr, L.T);         \
         else                                                                                                      \
-            hipLaunchKernelGGL((blocks_nucleon_kernel<float2, NTV, MODE>), dim3(blocks), dim3(kStagedThreads), 0,  \
+            hipLaunchKernelGGL((blocks_nucleon_kernel<float2, NTV, MODE>), dim3(blocks), dim3(kNucThreads), 0,     \
                                s, (const float2 *)L.Su, (const float2 *)L.Sd, L.nuc, L.V, L.chunk_sites,           \
                                L.n_chunks, L.K, (int)work, (double2 *)L.partial, nullptr, nullptr, L.T);         \
         done = true;                                                                                              \
@@ -858,44 +1026,72 @@ hipError_t launch_blocks(const BlockLaunch &L, hipStream_t s)
     return hipGetLastError();
 }
 
-size_t contract_lds_bytes(int K) { return (size_t)K * 792 * sizeof(double2); }
+size_t contract_tg_lds_bytes(int K, int tg) { return (size_t)(kMaxPalette + (size_t)tg * K * 792) * sizeof(double2); }
 
 namespace {
-template <int A, bool REAL>
-void dispatch_lds(const ContractLaunch &L, hipStream_t s, unsigned blocks, bool lds)
+// Dynamic LDS above the 64 KiB default needs an explicit opt-in per kernel;
+// the largest term-sum request (palette + 12 blocks) plus the kernels'
+// static LDS stays within the 160 KiB of a CU.
+constexpr size_t kMaxContractLds = (kMaxPalette + kMaxLdsKinds * 792) * sizeof(double2);
+template <typename F> hipError_t allow_lds(F *kernel)
 {
-    if (lds) {
-        // LDS above the 64 KiB default needs an explicit opt-in per kernel
-        static const hipError_t attr = hipFuncSetAttribute(
-            (const void *)contract_kernel<A, REAL, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
-        (void)attr;
-        hipLaunchKernelGGL((contract_kernel<A, REAL, true>), dim3(blocks), dim3(256), contract_lds_bytes(L.K), s,
-                           (const double2 *)L.B, L.kidx, L.coef, L.N, L.K, L.n_ct, L.n_slices, L.slice_len,
-                           (double2 *)L.partial);
-    } else
-        hipLaunchKernelGGL((contract_kernel<A, REAL, false>), dim3(blocks), dim3(256), 0, s, (const double2 *)L.B,
-                           L.kidx, L.coef, L.N, L.K, L.n_ct, L.n_slices, L.slice_len, (double2 *)L.partial);
+    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxContractLds);
 }
-template <int A>
-void dispatch_real(const ContractLaunch &L, hipStream_t s, unsigned blocks, bool lds)
+
+template <int A, bool PACKED> hipError_t launch_tg(const ContractLaunch &L, hipStream_t s, unsigned blocks)
 {
-    if (L.coef_real) dispatch_lds<A, true>(L, s, blocks, lds);
-    else dispatch_lds<A, false>(L, s, blocks, lds);
+    static const hipError_t attr = allow_lds(contract_tg_kernel<A, PACKED>);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((contract_tg_kernel<A, PACKED>), dim3(blocks), dim3(kCThreads),
+                       contract_tg_lds_bytes(L.K, L.tg), s, (const double2 *)L.B, L.tab, L.N, L.K, L.n_ct, L.tg,
+                       L.n_slices, L.slice_len, (double2 *)L.partial);
+    return hipSuccess;
+}
+
+template <int A> void launch_global(const ContractLaunch &L, hipStream_t s, unsigned blocks)
+{
+    if (L.tab.coef_real)
+        hipLaunchKernelGGL((contract_kernel<A, true>), dim3(blocks), dim3(256), 0, s, (const double2 *)L.B,
+                           L.tab.kidx, L.tab.coef, L.N, L.K, L.n_ct, L.n_slices, L.slice_len, (double2 *)L.partial);
+    else
+        hipLaunchKernelGGL((contract_kernel<A, false>), dim3(blocks), dim3(256), 0, s, (const double2 *)L.B,
+                           L.tab.kidx, L.tab.coef, L.N, L.K, L.n_ct, L.n_slices, L.slice_len, (double2 *)L.partial);
 }
 }  // namespace
 
 hipError_t launch_contract(const ContractLaunch &L, hipStream_t s)
 {
-    const unsigned blocks = (unsigned)round8((int64_t)L.n_ct * L.n_slices);
-    const bool lds = contract_lds_bytes(L.K) <= 160 * 1024 - 256;
     Probe pr("contract", s);
-    switch (L.A) {
-    case 1: dispatch_real<1>(L, s, blocks, lds); break;
-    case 2: dispatch_real<2>(L, s, blocks, lds); break;
-    case 3: dispatch_real<3>(L, s, blocks, lds); break;
-    case 4: dispatch_real<4>(L, s, blocks, lds); break;
-    case 5: dispatch_real<5>(L, s, blocks, lds); break;
-    default: return hipErrorInvalidValue;
+    if (L.tg > 0) {
+        if (L.tg > kMaxTG || L.tg * L.K > kMaxLdsKinds) return hipErrorInvalidValue;
+        const int64_t n_groups = (L.n_ct + L.tg - 1) / L.tg;
+        const unsigned blocks = (unsigned)round8(n_groups * L.n_slices);
+        const bool packed = L.tab.words != nullptr;
+        hipError_t e = hipErrorInvalidValue;
+        switch (L.A * 2 + (packed ? 1 : 0)) {
+        case 2: e = launch_tg<1, false>(L, s, blocks); break;
+        case 3: e = launch_tg<1, true>(L, s, blocks); break;
+        case 4: e = launch_tg<2, false>(L, s, blocks); break;
+        case 5: e = launch_tg<2, true>(L, s, blocks); break;
+        case 6: e = launch_tg<3, false>(L, s, blocks); break;
+        case 7: e = launch_tg<3, true>(L, s, blocks); break;
+        case 8: e = launch_tg<4, false>(L, s, blocks); break;
+        case 9: e = launch_tg<4, true>(L, s, blocks); break;
+        case 10: e = launch_tg<5, false>(L, s, blocks); break;
+        default: break;
+        }
+        if (e != hipSuccess) return e;
+    } else {
+        if (L.tab.words) return hipErrorInvalidValue;  // the global-memory kernel reads the plain table
+        const unsigned blocks = (unsigned)round8((int64_t)L.n_ct * L.n_slices);
+        switch (L.A) {
+        case 1: launch_global<1>(L, s, blocks); break;
+        case 2: launch_global<2>(L, s, blocks); break;
+        case 3: launch_global<3>(L, s, blocks); break;
+        case 4: launch_global<4>(L, s, blocks); break;
+        case 5: launch_global<5>(L, s, blocks); break;
+        default: return hipErrorInvalidValue;
+        }
     }
     pr.stop();
     hipError_t e = hipGetLastError();
@@ -907,21 +1103,27 @@ hipError_t launch_contract(const ContractLaunch &L, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 
 hipError_t launch_batch(const BatchLaunch &L, hipStream_t s)
 {
     {
         Probe pr("blocks", s);
-        const unsigned blocks = (unsigned)round8(L.n_bwork);
+        const unsigned blocks = (unsigned)round8((int64_t)L.n_bwork * kNucColGroups);
         bool done = false;
 #define WICK_BNUC(NTV, MODE)                                                                                      \
     if (L.nt_max == NTV && L.prec == MODE) {                                                                      \
         if (L.dtype == 0)                                                                                         \
-            hipLaunchKernelGGL((blocks_nucleon_kernel<double2, NTV, MODE>), dim3(blocks), dim3(kStagedThreads), 0, \
+            hipLaunchKernelGGL((blocks_nucleon_kernel<double2, NTV, MODE>), dim3(blocks), dim3(kNucThreads), 0,    \
                                s, (const double2 *)L.Su, (const double2 *)L.Sd, nullptr, L.V, L.chunk_sites, 0, 0, \
                                L.n_bwork, (double2 *)L.partial, L.bitems, L.bwork, L.T);                         \
         else                                                                                                      \
-            hipLaunchKernelGGL((blocks_nucleon_kernel<float2, NTV, MODE>), dim3(blocks), dim3(kStagedThreads), 0,  \
+            hipLaunchKernelGGL((blocks_nucleon_kernel<float2, NTV, MODE>), dim3(blocks), dim3(kNucThreads), 0,     \
                                s, (const float2 *)L.Su, (const float2 *)L.Sd, nullptr, L.V, L.chunk_sites, 0, 0,   \
                                L.n_bwork, (double2 *)L.partial, L.bitems, L.bwork, L.T);                         \
         done = true;                                                                                              \
@@ -946,14 +1148,11 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t s)
     }
     {
         Probe pr("contract", s);
-        const size_t lds = contract_lds_bytes(L.max_K);
-        if (lds > 160 * 1024 - 256) return hipErrorInvalidValue;
-        static const hipError_t attr = hipFuncSetAttribute((const void *)contract_batch_kernel,
-                                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                           160 * 1024 - 256);
-        (void)attr;
-        hipLaunchKernelGGL(contract_batch_kernel, dim3((unsigned)round8(L.n_cwork)), dim3(256), lds, s,
-                           (const double2 *)L.B, L.citems, L.cwork, L.n_cwork, (double2 *)L.cpartial);
+        if (L.contract_lds > kMaxContractLds) return hipErrorInvalidValue;
+        static const hipError_t attr = allow_lds(contract_batch_kernel);
+        if (attr != hipSuccess) return attr;
+        hipLaunchKernelGGL(contract_batch_kernel, dim3((unsigned)round8(L.n_cwork)), dim3(kCThreads), L.contract_lds,
+                           s, (const double2 *)L.B, L.citems, L.cwork, L.n_cwork, (double2 *)L.cpartial);
         pr.stop();
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -41,7 +41,7 @@ struct BlocksDesc {
 // S_f(x)[3 s3 + ., i3])_r, and Aop_k(x, r)[i1] = S_f(x)[3 alpha_k + r, i1].
 struct NucGroupDev {
     int32_t f, g, npair, nk;
-    int8_t s2[16], s3[16], m[16];
+    int32_t s2[16], s3[16], m[16];  // 32-bit: read with scalar loads
     int32_t alpha[kMaxKindsPerGroup], kind_out[kMaxKindsPerGroup];
 };
 struct NucDesc {
@@ -65,14 +65,37 @@ struct BatchBlockItem {
 struct BatchBlockWork {
     int32_t item, t, chunk, pass;
 };
-struct BatchContractItem {
-    const uint16_t *kidx;
+// Term table on the device. Packed form (A <= 4, K <= 20, at most 256
+// distinct coefficients): one 64-bit word per term holding the A block
+// indices kind*792 + c in 14-bit fields (field a at bit 14a) and, in the top
+// 8 bits, the index of the term's coefficient in a palette. Plain form:
+// kidx[A][N] uint16 and coef[N] (real) or coef[N][2].
+constexpr int kPackBits = 14;
+constexpr int kMaxPalette = 256;
+struct TermTable {
+    const uint64_t *words;  // packed [N], or null
+    const double2 *pal;     // packed: palette [n_pal]
+    int32_t n_pal;
+    int32_t coef_real;      // plain: coef is [N] (1) or [N][2] (0)
+    const uint16_t *kidx;   // plain [A][N]
     const double *coef;
+};
+
+// The term sum stages the blocks of up to kMaxTG consecutive time slices of
+// one (configuration or item) in LDS and reads each table word once for all
+// of them: tg * K <= kMaxLdsKinds keeps a workgroup within 160 KiB of LDS.
+constexpr int kCThreads = 1024;
+constexpr int kMaxTG = 3;
+constexpr int kMaxLdsKinds = 12;
+size_t contract_tg_lds_bytes(int K, int tg);  // palette + tg slices of K blocks
+
+struct BatchContractItem {
+    TermTable tab;
     int64_t N, slice_len, b_off, part_off;  // part_off: first partial of (item, t = 0)
-    int32_t A, K, coef_real, n_slices;
+    int32_t A, K, n_slices, tg;
 };
 struct BatchContractWork {
-    int32_t item, t, slice, pad;
+    int32_t item, t0, slice, ntg;
 };
 
 struct BlockLaunch {
@@ -108,7 +131,8 @@ struct BatchLaunch {
     int64_t n_bout;
     const BatchContractItem *citems;  // device
     const BatchContractWork *cwork;   // device
-    int n_cwork, max_K;
+    int n_cwork;
+    size_t contract_lds;              // dynamic LDS of the batched term sum
     double *partial;                  // workspace: raw partial blocks of every item
     double *B;                        // blocks of every item
     double *cpartial;                 // contraction partials
@@ -118,12 +142,11 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t s);
 
 struct ContractLaunch {
     const double *B;         // [n_ct][K][792][2]
-    const uint16_t *kidx;    // [A][N]
-    const double *coef;      // [N] or [N][2]
-    bool coef_real;
+    TermTable tab;
     int A, K;
     int64_t N;
     int n_ct;
+    int tg;                  // time slices per workgroup (LDS kernel); 0: blocks read from global memory
     int n_slices;
     int64_t slice_len;
     double *partial;         // [n_ct][n_slices][2]
@@ -131,8 +154,7 @@ struct ContractLaunch {
 };
 
 hipError_t launch_contract(const ContractLaunch &L, hipStream_t s);
-
-size_t contract_lds_bytes(int K);
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s);  // p[0..n) = 0 (a kernel, so graph capture is safe)
 
 // Optional per-kernel event timing (api.hip). A Probe records a start event
 // on construction and a stop event on stop() when profiling is enabled.
