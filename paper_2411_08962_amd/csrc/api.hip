@@ -96,9 +96,13 @@ struct DevPlan {
     BlocksDesc *desc = nullptr;  // null when the staged kernel does not apply
     uint16_t *kidx = nullptr;  // plain table (null when packed)
     double *coef = nullptr;
-    uint64_t *words = nullptr;  // packed table (null when plain)
+    uint64_t *words = nullptr;  // packed or segmented table (null when plain)
     double2 *pal = nullptr;
     int n_pal = 0;
+    uint32_t *seg_prefix = nullptr;  // segmented table only
+    int64_t *chunk_base = nullptr;
+    int32_t *chunk_len = nullptr;
+    int n_chunks = 0, seg_len = 0;
 };
 
 TermTable table_of(const DevPlan *d, const wick_plan_s *p)
@@ -110,7 +114,124 @@ TermTable table_of(const DevPlan *d, const wick_plan_s *p)
     t.coef_real = p->coef_real ? 1 : 0;
     t.kidx = d->kidx;
     t.coef = d->coef;
+    t.seg_prefix = d->seg_prefix;
+    t.chunk_base = d->chunk_base;
+    t.chunk_len = d->chunk_len;
+    t.n_chunks = d->n_chunks;
     return t;
+}
+
+// Palette index of every term (entry 0 of the palette is zero when `zero`
+// is set); false when the table has more distinct coefficients than fit.
+bool palette_of(const wick_plan_s *p, bool zero, std::vector<uint8_t> &idx, std::vector<double2> &pal)
+{
+    const size_t nt = (size_t)p->n_terms;
+    idx.assign(nt, 0);
+    pal.clear();
+    if (zero) pal.push_back(double2{0.0, 0.0});
+    int last = -1;
+    for (size_t n = 0; n < nt; ++n) {
+        const double re = p->coef_re[n], im = p->coef_im[n];
+        int c = -1;
+        if (last >= 0 && pal[last].x == re && pal[last].y == im) c = last;
+        for (int i = 0; c < 0 && i < (int)pal.size(); ++i)
+            if (pal[i].x == re && pal[i].y == im) c = i;
+        if (c < 0) {
+            if ((int)pal.size() == kMaxPalette) return false;
+            c = (int)pal.size();
+            pal.push_back(double2{re, im});
+        }
+        last = c;
+        idx[n] = (uint8_t)c;
+    }
+    return true;
+}
+
+// Host image of the segmented form of a table (see TermTable).
+struct SegTable {
+    std::vector<uint64_t> words;
+    std::vector<uint32_t> prefix;
+    std::vector<int64_t> base;
+    std::vector<int32_t> len;
+    std::vector<double2> pal;
+    int seg_len = 0;
+};
+
+bool segment_table(const wick_plan_s *p, SegTable &out)
+{
+    const int A = p->A;
+    const size_t nt = (size_t)p->n_terms;
+    if (A < 2 || A > 4 || (int)p->kinds.size() > kMaxLdsKinds || nt == 0 || nt > 0xffffffffULL) return false;
+    std::vector<uint8_t> pidx;
+    if (!palette_of(p, true, pidx, out.pal)) return false;
+    const uint16_t *k = p->kidx.data();
+    auto ix = [&](int a, uint32_t t) { return (uint32_t)k[(size_t)a * nt + t]; };
+    // terms in lexicographic order of their index tuples (LSD radix sort, 14-bit digits)
+    std::vector<uint32_t> ord(nt), tmp(nt);
+    for (size_t t = 0; t < nt; ++t) ord[t] = (uint32_t)t;
+    std::vector<size_t> cnt((size_t)1 << kPackBits);
+    for (int a = A - 1; a >= 0; --a) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (size_t i = 0; i < nt; ++i) ++cnt[ix(a, ord[i])];
+        size_t acc = 0;
+        for (auto &c : cnt) { const size_t v = c; c = acc; acc += v; }
+        for (size_t i = 0; i < nt; ++i) tmp[cnt[ix(a, ord[i])]++] = ord[i];
+        ord.swap(tmp);
+    }
+    // segments: runs sharing the first A-2 indices, at most seg_len terms
+    const int seg_len = (int)std::min<size_t>(128, std::max<size_t>(16, nt / 65536));
+    out.seg_len = seg_len;
+    auto prefix_of = [&](uint32_t t) {
+        uint32_t v = 0;
+        for (int a = 0; a < A - 2; ++a) v |= ix(a, t) << (kPackBits * a);
+        return v;
+    };
+    std::vector<std::pair<uint32_t, uint32_t>> segs;  // (start in ord, length)
+    for (size_t i = 0; i < nt;) {
+        const uint32_t pre = prefix_of(ord[i]);
+        size_t j = i + 1;
+        while (j < nt && j - i < (size_t)seg_len && prefix_of(ord[j]) == pre) ++j;
+        segs.push_back({(uint32_t)i, (uint32_t)(j - i)});
+        i = j;
+    }
+    std::stable_sort(segs.begin(), segs.end(), [](const auto &x, const auto &y) { return x.second > y.second; });
+    const size_t n_chunks = (segs.size() + 63) / 64;
+    out.prefix.assign(n_chunks * 64, 0);
+    out.base.resize(n_chunks);
+    out.len.resize(n_chunks);
+    size_t total = 0;
+    for (size_t c = 0; c < n_chunks; ++c) {
+        out.base[c] = (int64_t)total;
+        out.len[c] = (int32_t)segs[c * 64].second;
+        total += (size_t)out.len[c] * 64;
+    }
+    out.words.assign(total, 0);
+    for (size_t c = 0; c < n_chunks; ++c) {
+        for (int lane = 0; lane < 64; ++lane) {
+            const size_t si = c * 64 + lane;
+            const int L = out.len[c];
+            uint64_t *w = out.words.data() + out.base[c] + lane;
+            if (si >= segs.size()) {  // an empty lane: zero-coefficient words
+                for (int j = 0; j < L; ++j) w[(size_t)j * 64] = j == 0 ? (1ull << 36) : 0;
+                continue;
+            }
+            const uint32_t st = segs[si].first, n = segs[si].second;
+            out.prefix[si] = prefix_of(ord[st]);
+            for (int j = 0; j < L; ++j) {
+                uint64_t v;
+                if ((uint32_t)j < n) {
+                    const uint32_t t = ord[st + j];
+                    const bool nn = j == 0 || ix(A - 2, t) != ix(A - 2, ord[st + j - 1]);
+                    v = (uint64_t)ix(A - 1, t) | ((uint64_t)ix(A - 2, t) << kPackBits) | ((uint64_t)pidx[t] << (2 * kPackBits)) |
+                        ((uint64_t)nn << 36);
+                } else {
+                    v = 0;  // padding: zero coefficient, same node
+                }
+                w[(size_t)j * 64] = v;
+            }
+        }
+    }
+    return true;
 }
 
 // The packed form of a table (see TermTable), or false when it does not apply.
@@ -295,35 +416,61 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
         }
     }
     const size_t nt = (size_t)p->n_terms;
+    // table form: packed where it applies, else plain; WICK_TABLE_FORM=
+    // plain|packed|segmented selects one (the prefix-shared segmented form
+    // measured no faster than the packed one on the built-in tables)
+    const char *form_env = std::getenv("WICK_TABLE_FORM");
+    const std::string form = form_env ? form_env : "";
     std::vector<uint64_t> words;
     std::vector<double2> pal;
-    const bool packed = pack_table(p, words, pal);
+    SegTable seg;
+    const bool packed = (form.empty() || form == "packed") && pack_table(p, words, pal);
+    const bool segmented = !packed && form == "segmented" && segment_table(p, seg);
+    if (segmented) {
+        words.swap(seg.words);
+        pal = seg.pal;
+    }
     const size_t coef_n = p->coef_real ? nt : 2 * nt;
     auto undo = [&] {
         for (void *q : {(void *)d.groups, (void *)d.desc, (void *)d.nuc, (void *)d.nuc_split, (void *)d.kidx,
-                        (void *)d.coef, (void *)d.words, (void *)d.pal})
+                        (void *)d.coef, (void *)d.words, (void *)d.pal, (void *)d.seg_prefix, (void *)d.chunk_base,
+                        (void *)d.chunk_len})
             if (q) (void)hipFree(q);
     };
+    const bool word_form = segmented || packed;
     if ((e = hipMalloc(&d.groups, std::max<size_t>(1, hg.size()) * sizeof(EGroupDev))) != hipSuccess ||
-        (packed && (e = hipMalloc(&d.words, nt * sizeof(uint64_t))) != hipSuccess) ||
-        (packed && (e = hipMalloc(&d.pal, pal.size() * sizeof(double2))) != hipSuccess) ||
-        (!packed && (e = hipMalloc(&d.kidx, std::max<size_t>(1, nt * p->A) * sizeof(uint16_t))) != hipSuccess) ||
-        (!packed && (e = hipMalloc(&d.coef, std::max<size_t>(1, coef_n) * sizeof(double))) != hipSuccess)) {
+        (word_form && (e = hipMalloc(&d.words, words.size() * sizeof(uint64_t))) != hipSuccess) ||
+        (word_form && (e = hipMalloc(&d.pal, pal.size() * sizeof(double2))) != hipSuccess) ||
+        (segmented && (e = hipMalloc(&d.seg_prefix, seg.prefix.size() * sizeof(uint32_t))) != hipSuccess) ||
+        (segmented && (e = hipMalloc(&d.chunk_base, seg.base.size() * sizeof(int64_t))) != hipSuccess) ||
+        (segmented && (e = hipMalloc(&d.chunk_len, seg.len.size() * sizeof(int32_t))) != hipSuccess) ||
+        (!word_form && (e = hipMalloc(&d.kidx, std::max<size_t>(1, nt * p->A) * sizeof(uint16_t))) != hipSuccess) ||
+        (!word_form && (e = hipMalloc(&d.coef, std::max<size_t>(1, coef_n) * sizeof(double))) != hipSuccess)) {
         undo();
         return fail(WICK_ENOMEM, std::string("plan upload hipMalloc: ") + hipGetErrorString(e));
     }
+    if (segmented) {
+        d.n_chunks = (int)seg.base.size();
+        d.seg_len = seg.seg_len;
+        if ((e = hipMemcpy(d.seg_prefix, seg.prefix.data(), seg.prefix.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(d.chunk_base, seg.base.data(), seg.base.size() * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(d.chunk_len, seg.len.data(), seg.len.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) {
+            undo();
+            return hip_fail(e, "plan upload hipMemcpy");
+        }
+    }
     d.n_pal = (int)pal.size();
-    std::vector<double> coef(packed ? 0 : coef_n);
-    for (size_t n = 0; n < nt && !packed; ++n) {
+    std::vector<double> coef(word_form ? 0 : coef_n);
+    for (size_t n = 0; n < nt && !word_form; ++n) {
         if (p->coef_real) coef[n] = p->coef_re[n];
         else { coef[2 * n] = p->coef_re[n]; coef[2 * n + 1] = p->coef_im[n]; }
     }
     // synchronous copies: the host staging vectors die at return
     if ((e = hipMemcpy(d.groups, hg.data(), hg.size() * sizeof(EGroupDev), hipMemcpyHostToDevice)) != hipSuccess ||
-        (packed && (e = hipMemcpy(d.words, words.data(), nt * sizeof(uint64_t), hipMemcpyHostToDevice)) != hipSuccess) ||
-        (packed && (e = hipMemcpy(d.pal, pal.data(), pal.size() * sizeof(double2), hipMemcpyHostToDevice)) != hipSuccess) ||
-        (!packed && nt && (e = hipMemcpy(d.kidx, p->kidx.data(), nt * p->A * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess) ||
-        (!packed && nt && (e = hipMemcpy(d.coef, coef.data(), coef_n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)) {
+        (word_form && (e = hipMemcpy(d.words, words.data(), words.size() * sizeof(uint64_t), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (word_form && (e = hipMemcpy(d.pal, pal.data(), pal.size() * sizeof(double2), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (!word_form && nt && (e = hipMemcpy(d.kidx, p->kidx.data(), nt * p->A * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (!word_form && nt && (e = hipMemcpy(d.coef, coef.data(), coef_n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)) {
         undo();
         return hip_fail(e, "plan upload hipMemcpy");
     }
@@ -379,6 +526,15 @@ int64_t default_slice_len(int64_t N, int64_t n_groups)
 {
     int64_t len = std::max<int64_t>(4096, (N * n_groups + 1023) / 1024);
     return (len + kCThreads - 1) / kCThreads * kCThreads;
+}
+
+// chunks of a segmented table per term-sum workgroup for a target number of
+// terms per workgroup: a multiple of the workgroup's 16 waves
+int64_t chunks_per_group(int64_t terms, int seg_len)
+{
+    const int64_t waves = kCThreads / 64;
+    const int64_t c = std::max<int64_t>(1, terms / (64 * (int64_t)seg_len));
+    return (c + waves - 1) / waves * waves;
 }
 
 // time slices per term-sum workgroup (0: the blocks do not fit in LDS)
@@ -476,7 +632,13 @@ wick_status do_contract(wick_plan_s *p, const double *B, int n_cfg, int T, hipSt
     const int64_t n_groups = L.tg ? (n_ct + L.tg - 1) / L.tg : n_ct;
     const int64_t sl = slice_override > 0 ? slice_override : tuned_slice(p, n_ct);
     L.slice_len = sl > 0 ? sl : default_slice_len(L.N, n_groups);
-    L.n_slices = (int)((L.N + L.slice_len - 1) / L.slice_len);
+    if (dp->seg_prefix) {
+        // terms per workgroup -> chunks per workgroup, a multiple of the 16 waves
+        L.slice_len = chunks_per_group(L.slice_len, dp->seg_len);
+        L.n_slices = (int)((dp->n_chunks + L.slice_len - 1) / L.slice_len);
+    } else {
+        L.n_slices = (int)((L.N + L.slice_len - 1) / L.slice_len);
+    }
     if ((int64_t)L.n_slices * n_groups > 0x7ffffff0LL) return fail(WICK_ETOOBIG, "wick_contract: grid too large");
     void *ws;
     if ((st = workspace(s, (size_t)n_ct * L.n_slices * 16, &ws)) != WICK_OK) return st;
@@ -623,8 +785,13 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
         BatchContractItem &c = ci[i];
         c.tab = table_of(dp, p);
         c.N = p->n_terms;
-        c.slice_len = S;
-        c.n_slices = (int)std::max<int64_t>(1, (c.N + S - 1) / S);
+        if (dp->seg_prefix) {
+            c.slice_len = chunks_per_group(S, dp->seg_len);
+            c.n_slices = (int)std::max<int64_t>(1, (dp->n_chunks + c.slice_len - 1) / c.slice_len);
+        } else {
+            c.slice_len = S;
+            c.n_slices = (int)std::max<int64_t>(1, (c.N + S - 1) / S);
+        }
         c.b_off = bi[i].b_off;
         c.part_off = cpart;
         c.A = p->A;
@@ -823,7 +990,7 @@ wick_status autotune(wick_plan_s *p, const int32_t dims[4], int dtype, int prec,
     if (p->n_terms > 0) {
         if ((st = do_blocks(p, sc.Su, sc.Sd, dtype, dims, 1, prec, sc.s, (double *)sc.B, best_chunk)) != WICK_OK)
             return st;
-        const int64_t scand[] = {1024, 2048, 4096, 8192, 16384, 32768, 65536, 262144};
+        const int64_t scand[] = {4096, 16384, 65536, 262144, 1048576, 4194304};
         best = 0.f;
         for (int64_t sl : scand) {
             if (sl >= 2 * p->n_terms && sl != scand[0]) break;
@@ -900,6 +1067,9 @@ void release_device_tables(wick_plan_s *p)
         (void)hipFree(d.coef);
         (void)hipFree(d.words);
         (void)hipFree(d.pal);
+        (void)hipFree(d.seg_prefix);
+        (void)hipFree(d.chunk_base);
+        (void)hipFree(d.chunk_len);
     }
     (void)hipSetDevice(cur);
     g_dev.erase(it);

@@ -735,27 +735,7 @@ __device__ __forceinline__ void term_sum(const double2 *__restrict__ sB, int KB,
                                          const double2 *__restrict__ spal, const TermTable &tab, int64_t N,
                                          int64_t n0, int64_t n1, double (&ar)[kMaxTG], double (&ai)[kMaxTG])
 {
-    for (int64_t n = n0 + threadIdx.x; n < n1; n += kCThreads) {
-        int idx[A];
-        double cx, cy;
-        if constexpr (PACKED) {
-            const uint64_t w = tab.words[n];
-#pragma unroll
-            for (int a = 0; a < A; ++a) idx[a] = (int)(w >> (kPackBits * a)) & ((1 << kPackBits) - 1);
-            const double2 c = spal[(int)(w >> 56)];
-            cx = c.x;
-            cy = c.y;
-        } else {
-#pragma unroll
-            for (int a = 0; a < A; ++a) idx[a] = tab.kidx[(int64_t)a * N + n];
-            if (tab.coef_real) {
-                cx = tab.coef[n];
-                cy = 0.0;
-            } else {
-                cx = tab.coef[2 * n];
-                cy = tab.coef[2 * n + 1];
-            }
-        }
+    auto eval = [&](const int (&idx)[A], double cx, double cy) {
 #pragma unroll
         for (int tg = 0; tg < kMaxTG; ++tg) {
             if (tg < ntg) {
@@ -768,6 +748,122 @@ __device__ __forceinline__ void term_sum(const double2 *__restrict__ sB, int KB,
                 }
                 ar[tg] += cx * p.x - cy * p.y;
                 ai[tg] += cx * p.y + cy * p.x;
+            }
+        }
+    };
+    if constexpr (PACKED) {
+        // this thread's terms n0 + tid + k * kCThreads; the words of the next
+        // kPrefetch terms are loaded while the current ones are evaluated
+        const int64_t first = n0 + threadIdx.x;
+        const int64_t cnt = first < n1 ? (n1 - first + kCThreads - 1) / kCThreads : 0;
+        uint64_t cur[kPrefetch], nxt[kPrefetch] = {};
+        auto fetch = [&](int64_t k0, uint64_t (&w)[kPrefetch]) {
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) w[u] = k0 + u < cnt ? tab.words[first + (k0 + u) * kCThreads] : 0;
+        };
+        fetch(0, cur);
+        for (int64_t k0 = 0; k0 < cnt; k0 += kPrefetch) {
+            if (k0 + kPrefetch < cnt) fetch(k0 + kPrefetch, nxt);
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) {
+                if (k0 + u < cnt) {
+                    const uint64_t w = cur[u];
+                    int idx[A];
+#pragma unroll
+                    for (int a = 0; a < A; ++a) idx[a] = (int)(w >> (kPackBits * a)) & ((1 << kPackBits) - 1);
+                    const double2 c = spal[(int)(w >> 56)];
+                    eval(idx, c.x, c.y);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) cur[u] = nxt[u];
+        }
+    } else {
+        for (int64_t n = n0 + threadIdx.x; n < n1; n += kCThreads) {
+            int idx[A];
+#pragma unroll
+            for (int a = 0; a < A; ++a) idx[a] = tab.kidx[(int64_t)a * N + n];
+            if (tab.coef_real) eval(idx, tab.coef[n], 0.0);
+            else eval(idx, tab.coef[2 * n], tab.coef[2 * n + 1]);
+        }
+    }
+}
+
+// Term sum over the chunks [c0, c1) of a segmented table: wave w of the
+// workgroup takes chunks c0 + w, c0 + w + 16, ...; each lane evaluates its
+// segment of the chunk for every staged slice (see TermTable).
+template <int A>
+__device__ __forceinline__ void term_sum_seg(const double2 *__restrict__ sB, int KB, int ntg,
+                                             const double2 *__restrict__ spal, const TermTable &tab, int c0, int c1,
+                                             double (&ar)[kMaxTG], double (&ai)[kMaxTG])
+{
+    constexpr uint32_t kMask = (1u << kPackBits) - 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int c = c0 + wave; c < c1; c += kCThreads / 64) {
+        const uint32_t pre = tab.seg_prefix[(int64_t)c * 64 + lane];
+        double px[kMaxTG], py[kMaxTG], s2x[kMaxTG], s2y[kMaxTG], s3x[kMaxTG], s3y[kMaxTG], bx[kMaxTG], by[kMaxTG];
+#pragma unroll
+        for (int tg = 0; tg < kMaxTG; ++tg) {
+            px[tg] = 1.0;
+            py[tg] = 0.0;
+            if (tg < ntg) {
+#pragma unroll
+                for (int a = 0; a < A - 2; ++a) {
+                    const double2 b = sB[tg * KB + ((pre >> (kPackBits * a)) & kMask)];
+                    const double x = px[tg] * b.x - py[tg] * b.y;
+                    py[tg] = px[tg] * b.y + py[tg] * b.x;
+                    px[tg] = x;
+                }
+            }
+            s2x[tg] = s2y[tg] = s3x[tg] = s3y[tg] = bx[tg] = by[tg] = 0.0;
+        }
+        const uint64_t *wp = tab.words + tab.chunk_base[c] + lane;
+        const int L = tab.chunk_len[c];
+        // the next kPrefetch words are loaded while the current ones are evaluated
+        uint64_t cur[kPrefetch], nxt[kPrefetch] = {};
+        auto fetch = [&](int j0, uint64_t (&w)[kPrefetch]) {
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) w[u] = j0 + u < L ? wp[(int64_t)(j0 + u) * 64] : 0;
+        };
+        fetch(0, cur);
+        for (int j0 = 0; j0 < L; j0 += kPrefetch) {
+            if (j0 + kPrefetch < L) fetch(j0 + kPrefetch, nxt);
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) {
+                if (j0 + u >= L) break;
+                const uint64_t w = cur[u];
+                const int il = (int)(w & kMask), in = (int)((w >> kPackBits) & kMask);
+                const double2 cf = spal[(int)(w >> (2 * kPackBits)) & 0xff];
+                const bool nn = (w >> 36) & 1;
+#pragma unroll
+                for (int tg = 0; tg < kMaxTG; ++tg) {
+                    if (tg < ntg) {
+                        const double2 *Bt = sB + tg * KB;
+                        if (nn) {
+                            // close the previous node: S2 += B[node] * S3
+                            s2x[tg] += bx[tg] * s3x[tg] - by[tg] * s3y[tg];
+                            s2y[tg] += bx[tg] * s3y[tg] + by[tg] * s3x[tg];
+                            s3x[tg] = s3y[tg] = 0.0;
+                            const double2 bn = Bt[in];
+                            bx[tg] = bn.x;
+                            by[tg] = bn.y;
+                        }
+                        const double2 b = Bt[il];
+                        s3x[tg] += cf.x * b.x - cf.y * b.y;
+                        s3y[tg] += cf.x * b.y + cf.y * b.x;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) cur[u] = nxt[u];
+        }
+#pragma unroll
+        for (int tg = 0; tg < kMaxTG; ++tg) {
+            if (tg < ntg) {
+                s2x[tg] += bx[tg] * s3x[tg] - by[tg] * s3y[tg];
+                s2y[tg] += bx[tg] * s3y[tg] + by[tg] * s3x[tg];
+                ar[tg] += px[tg] * s2x[tg] - py[tg] * s2y[tg];
+                ai[tg] += px[tg] * s2y[tg] + py[tg] * s2x[tg];
             }
         }
     }
@@ -816,8 +912,9 @@ __device__ __forceinline__ void reduce_tg(double (&ar)[kMaxTG], double (&ai)[kMa
     }
 }
 
-// One plan: workgroup (group of tg consecutive (cfg, t) sets, table slice).
-template <int A, bool PACKED>
+// One plan: workgroup (group of tg consecutive (cfg, t) sets, table slice);
+// a slice is slice_len terms (plain, packed) or slice_len chunks (segmented).
+template <int A, int FORM>
 __global__ __launch_bounds__(kCThreads) void contract_tg_kernel(const double2 *__restrict__ B, TermTable tab,
                                                                 int64_t N, int K, int n_ct, int tg, int n_slices,
                                                                 int64_t slice_len, double2 *__restrict__ partial)
@@ -832,10 +929,16 @@ __global__ __launch_bounds__(kCThreads) void contract_tg_kernel(const double2 *_
     const int KB = K * 792;
     double2 *spal = lds, *sB = lds + kMaxPalette;
     stage_blocks(B + (int64_t)ct0 * KB, ntg * KB, tab, sB, spal);
-    const int64_t n0 = (int64_t)slice * slice_len;
-    const int64_t n1 = n0 + slice_len < N ? n0 + slice_len : N;
     double ar[kMaxTG] = {}, ai[kMaxTG] = {};
-    term_sum<A, PACKED>(sB, KB, ntg, spal, tab, N, n0, n1, ar, ai);
+    if constexpr (FORM == 2) {
+        const int c0 = (int)(slice * slice_len);
+        const int c1 = c0 + slice_len < tab.n_chunks ? (int)(c0 + slice_len) : tab.n_chunks;
+        term_sum_seg<A>(sB, KB, ntg, spal, tab, c0, c1, ar, ai);
+    } else {
+        const int64_t n0 = (int64_t)slice * slice_len;
+        const int64_t n1 = n0 + slice_len < N ? n0 + slice_len : N;
+        term_sum<A, FORM == 1>(sB, KB, ntg, spal, tab, N, n0, n1, ar, ai);
+    }
     reduce_tg(ar, ai, ntg, red, partial + (int64_t)ct0 * n_slices + slice, n_slices);
 }
 
@@ -913,9 +1016,21 @@ __global__ __launch_bounds__(kCThreads) void contract_batch_kernel(const double2
     const int KB = it.K * 792, ntg = w.ntg;
     double2 *spal = lds, *sB = lds + kMaxPalette;
     stage_blocks(B + it.b_off + (int64_t)w.t0 * KB, ntg * KB, it.tab, sB, spal);
+    double ar[kMaxTG] = {}, ai[kMaxTG] = {};
+    if (it.tab.seg_prefix) {
+        const int c0 = (int)(w.slice * it.slice_len);
+        const int c1 = c0 + it.slice_len < it.tab.n_chunks ? (int)(c0 + it.slice_len) : it.tab.n_chunks;
+        switch (it.A) {
+        case 2: term_sum_seg<2>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
+        case 3: term_sum_seg<3>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
+        case 4: term_sum_seg<4>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
+        default: break;
+        }
+        reduce_tg(ar, ai, ntg, red, partial + it.part_off + (int64_t)w.t0 * it.n_slices + w.slice, it.n_slices);
+        return;
+    }
     const int64_t n0 = (int64_t)w.slice * it.slice_len;
     const int64_t n1 = n0 + it.slice_len < it.N ? n0 + it.slice_len : it.N;
-    double ar[kMaxTG] = {}, ai[kMaxTG] = {};
     const bool packed = it.tab.words != nullptr;
     switch (it.A * 2 + (packed ? 1 : 0)) {
     case 2: term_sum<1, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
@@ -1038,11 +1153,11 @@ template <typename F> hipError_t allow_lds(F *kernel)
     return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxContractLds);
 }
 
-template <int A, bool PACKED> hipError_t launch_tg(const ContractLaunch &L, hipStream_t s, unsigned blocks)
+template <int A, int FORM> hipError_t launch_tg(const ContractLaunch &L, hipStream_t s, unsigned blocks)
 {
-    static const hipError_t attr = allow_lds(contract_tg_kernel<A, PACKED>);
+    static const hipError_t attr = allow_lds(contract_tg_kernel<A, FORM>);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((contract_tg_kernel<A, PACKED>), dim3(blocks), dim3(kCThreads),
+    hipLaunchKernelGGL((contract_tg_kernel<A, FORM>), dim3(blocks), dim3(kCThreads),
                        contract_tg_lds_bytes(L.K, L.tg), s, (const double2 *)L.B, L.tab, L.N, L.K, L.n_ct, L.tg,
                        L.n_slices, L.slice_len, (double2 *)L.partial);
     return hipSuccess;
@@ -1066,18 +1181,21 @@ hipError_t launch_contract(const ContractLaunch &L, hipStream_t s)
         if (L.tg > kMaxTG || L.tg * L.K > kMaxLdsKinds) return hipErrorInvalidValue;
         const int64_t n_groups = (L.n_ct + L.tg - 1) / L.tg;
         const unsigned blocks = (unsigned)round8(n_groups * L.n_slices);
-        const bool packed = L.tab.words != nullptr;
+        const int form = L.tab.seg_prefix ? 2 : (L.tab.words ? 1 : 0);
         hipError_t e = hipErrorInvalidValue;
-        switch (L.A * 2 + (packed ? 1 : 0)) {
-        case 2: e = launch_tg<1, false>(L, s, blocks); break;
-        case 3: e = launch_tg<1, true>(L, s, blocks); break;
-        case 4: e = launch_tg<2, false>(L, s, blocks); break;
-        case 5: e = launch_tg<2, true>(L, s, blocks); break;
-        case 6: e = launch_tg<3, false>(L, s, blocks); break;
-        case 7: e = launch_tg<3, true>(L, s, blocks); break;
-        case 8: e = launch_tg<4, false>(L, s, blocks); break;
-        case 9: e = launch_tg<4, true>(L, s, blocks); break;
-        case 10: e = launch_tg<5, false>(L, s, blocks); break;
+        switch (L.A * 3 + form) {
+        case 3: e = launch_tg<1, 0>(L, s, blocks); break;
+        case 4: e = launch_tg<1, 1>(L, s, blocks); break;
+        case 6: e = launch_tg<2, 0>(L, s, blocks); break;
+        case 7: e = launch_tg<2, 1>(L, s, blocks); break;
+        case 8: e = launch_tg<2, 2>(L, s, blocks); break;
+        case 9: e = launch_tg<3, 0>(L, s, blocks); break;
+        case 10: e = launch_tg<3, 1>(L, s, blocks); break;
+        case 11: e = launch_tg<3, 2>(L, s, blocks); break;
+        case 12: e = launch_tg<4, 0>(L, s, blocks); break;
+        case 13: e = launch_tg<4, 1>(L, s, blocks); break;
+        case 14: e = launch_tg<4, 2>(L, s, blocks); break;
+        case 15: e = launch_tg<5, 0>(L, s, blocks); break;
         default: break;
         }
         if (e != hipSuccess) return e;

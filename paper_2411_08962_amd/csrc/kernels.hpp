@@ -72,13 +72,31 @@ struct BatchBlockWork {
 // kidx[A][N] uint16 and coef[N] (real) or coef[N][2].
 constexpr int kPackBits = 14;
 constexpr int kMaxPalette = 256;
+//
+// Segmented form (2 <= A <= 4, K <= 12, at most 255 distinct coefficients),
+// which shares the leading indices of the terms: the table sorted by its
+// index tuples is cut into segments of at most seg_len terms that share the
+// first A-2 indices (the segment prefix); within a segment the terms come in
+// runs ("nodes") sharing index A-2. A lane evaluates one segment as
+//   P * sum_nodes B[node] * sum_leaves coef * B[leaf],   P = prod of the prefix entries,
+// so each term costs one LDS gather plus one per node instead of A. Segments
+// are sorted by length and dealt to the 64 lanes of a chunk; chunk c holds
+// chunk_len[c] words per lane, interleaved (word j of lane l at
+// chunk_base[c] + 64 j + l) so a wave reads 64 consecutive words per step;
+// shorter segments are padded with zero-coefficient words. Word bits: leaf
+// index [0,14), node index [14,28), palette index [28,36), new-node flag 36.
 struct TermTable {
-    const uint64_t *words;  // packed [N], or null
-    const double2 *pal;     // packed: palette [n_pal]
+    const uint64_t *words;  // packed [N] or segmented (interleaved chunks), or null
+    const double2 *pal;     // packed / segmented: palette [n_pal]
     int32_t n_pal;
     int32_t coef_real;      // plain: coef is [N] (1) or [N][2] (0)
     const uint16_t *kidx;   // plain [A][N]
     const double *coef;
+    // segmented form (seg_prefix != null)
+    const uint32_t *seg_prefix;  // [n_chunks * 64]: A-2 indices of 14 bits
+    const int64_t *chunk_base;   // [n_chunks]
+    const int32_t *chunk_len;    // [n_chunks]
+    int32_t n_chunks;
 };
 
 // The term sum stages the blocks of up to kMaxTG consecutive time slices of
@@ -87,11 +105,12 @@ struct TermTable {
 constexpr int kCThreads = 1024;
 constexpr int kMaxTG = 3;
 constexpr int kMaxLdsKinds = 12;
+constexpr int kPrefetch = 8;  // table words in flight per lane in the term sum
 size_t contract_tg_lds_bytes(int K, int tg);  // palette + tg slices of K blocks
 
 struct BatchContractItem {
     TermTable tab;
-    int64_t N, slice_len, b_off, part_off;  // part_off: first partial of (item, t = 0)
+    int64_t N, slice_len, b_off, part_off;  // part_off: first partial of (item, t = 0); slice_len in chunks when segmented
     int32_t A, K, n_slices, tg;
 };
 struct BatchContractWork {
@@ -148,7 +167,7 @@ struct ContractLaunch {
     int n_ct;
     int tg;                  // time slices per workgroup (LDS kernel); 0: blocks read from global memory
     int n_slices;
-    int64_t slice_len;
+    int64_t slice_len;       // terms per workgroup (chunks per workgroup for a segmented table)
     double *partial;         // [n_ct][n_slices][2]
     double *C;               // [n_ct][2]
 };

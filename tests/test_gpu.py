@@ -286,3 +286,30 @@ def test_autotune_cache_and_parity(tmp_path, name, dims, prec):
     check_C(ops.by_name(name), pl, C, hu, hd, range(dims[3]), tol=tol)
     Cb = w.correlator([pl], [(0, 0)], du, dd, prec).cpu().numpy()
     check_C(ops.by_name(name), pl, Cb, hu, hd, range(dims[3]), tol=tol)
+
+
+# ------------------------------------------------------------- table forms
+@pytest.mark.parametrize("form", ["plain", "packed", "segmented"])
+@pytest.mark.parametrize("name,dims", [("2H", (3, 2, 2, 3)), ("3He", (3, 1, 1, 2)), ("3H", (2, 2, 1, 4))])
+def test_term_table_forms(monkeypatch, form, name, dims):
+    """Every device form of the term table (plain indices, packed words,
+    prefix-shared segments) gives the oracle's C(t) through wick_contract
+    and through the batched path."""
+    monkeypatch.setenv("WICK_TABLE_FORM", form)
+    w = W()
+    pl = w.plan_std(name)  # a fresh plan: its device table is built under this form
+    hu, hd, du, dd = props(14, 1, dims)
+    C = w.contract(pl, w.blocks(pl, du, dd)).cpu().numpy()
+    check_C(ops.by_name(name), pl, C, hu, hd, range(dims[3]))
+    Cb = w.correlator([pl], [(0, 0)], du, dd).cpu().numpy()
+    check_C(ops.by_name(name), pl, Cb, hu, hd, range(dims[3]))
+
+
+def test_proton_single_nucleon_table():
+    # A = 1: the packed form without prefix sharing
+    w = W()
+    for a in range(4):
+        pl = w.plan_std("1H", a)
+        hu, hd, du, dd = props(15, 1, (2, 2, 2, 3))
+        C = w.contract(pl, w.blocks(pl, du, dd)).cpu().numpy()
+        check_C(ops.proton(a), pl, C, hu, hd, range(3))
