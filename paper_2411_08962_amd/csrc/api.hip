@@ -383,10 +383,18 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
                 h.g = ng.g;
                 h.npair = (int)ng.pairs.size();
                 h.nk = (int)ng.kinds.size();
+                // diquark entries ordered M = +1, M = -1, other values (the kernel
+                // folds a unit M into the sign pattern of its FMA chains)
+                std::vector<std::array<int8_t, 3>> pr(ng.pairs.begin(), ng.pairs.end());
+                auto cls = [](int m) { return m == 1 ? 0 : (m == -1 ? 1 : 2); };
+                std::stable_sort(pr.begin(), pr.end(), [&](const auto &x, const auto &y) { return cls(x[2]) < cls(y[2]); });
+                h.npos = h.nneg = 0;
                 for (int i = 0; i < h.npair; ++i) {
-                    h.s2[i] = ng.pairs[i][0];
-                    h.s3[i] = ng.pairs[i][1];
-                    h.m[i] = ng.pairs[i][2];
+                    h.s2[i] = pr[i][0];
+                    h.s3[i] = pr[i][1];
+                    h.m[i] = pr[i][2];
+                    h.npos += pr[i][2] == 1;
+                    h.nneg += pr[i][2] == -1;
                 }
                 for (int k = 0; k < h.nk; ++k) {
                     h.alpha[k] = ng.alpha[k];

@@ -492,19 +492,39 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
                 const TIn *sfb = buf[G.f][s];
                 const TIn *sgb = buf[G.g][s];
                 double e0x = 0, e0y = 0, e1x = 0, e1y = 0, e2x = 0, e2y = 0;
-                for (int p = 0; p < G.npair; ++p) {
+                // E_r += M * sum eps[r][c3][c2] a_c2 b_c3 with a = S_g(3 s2 + ., i2),
+                // b = S_f(3 s3 + ., i3): E_0 += a2 b1 - a1 b2, E_1 += a0 b2 - a2 b0,
+                // E_2 += a1 b0 - a0 b1, accumulated as FMA chains; M = -1 swaps the
+                // roles of the two products, other values scale them
+                auto cross = [&](int p, double sgn, double scale) {
                     const TIn *pa = sgb + 36 * G.s2[p] + i2;
                     const TIn *pb = sfb + 36 * G.s3[p] + i3;
-                    const double2 a0 = rd(pa), a1 = rd(pa + 12), a2 = rd(pa + 24);
+                    double2 a0 = rd(pa), a1 = rd(pa + 12), a2 = rd(pa + 24);
                     const double2 b0 = rd(pb), b1 = rd(pb + 12), b2 = rd(pb + 24);
-                    const double m = (double)G.m[p];
-                    // E_r = M * sum eps[r][c3][c2] a_c2 b_c3
-                    e0x += m * ((a2.x * b1.x - a2.y * b1.y) - (a1.x * b2.x - a1.y * b2.y));
-                    e0y += m * ((a2.x * b1.y + a2.y * b1.x) - (a1.x * b2.y + a1.y * b2.x));
-                    e1x += m * ((a0.x * b2.x - a0.y * b2.y) - (a2.x * b0.x - a2.y * b0.y));
-                    e1y += m * ((a0.x * b2.y + a0.y * b2.x) - (a2.x * b0.y + a2.y * b0.x));
-                    e2x += m * ((a1.x * b0.x - a1.y * b0.y) - (a0.x * b1.x - a0.y * b1.y));
-                    e2y += m * ((a1.x * b0.y + a1.y * b0.x) - (a0.x * b1.y + a0.y * b1.x));
+                    if (scale != 1.0) {
+                        a0 = double2{a0.x * scale, a0.y * scale};
+                        a1 = double2{a1.x * scale, a1.y * scale};
+                        a2 = double2{a2.x * scale, a2.y * scale};
+                    }
+                    auto acc2 = [&](double &ex, double &ey, double2 u, double2 v, double s) {
+                        // (ex, ey) += s * u * v
+                        ex = fma(s * u.x, v.x, ex);
+                        ex = fma(-s * u.y, v.y, ex);
+                        ey = fma(s * u.x, v.y, ey);
+                        ey = fma(s * u.y, v.x, ey);
+                    };
+                    acc2(e0x, e0y, a2, b1, sgn);
+                    acc2(e0x, e0y, a1, b2, -sgn);
+                    acc2(e1x, e1y, a0, b2, sgn);
+                    acc2(e1x, e1y, a2, b0, -sgn);
+                    acc2(e2x, e2y, a1, b0, sgn);
+                    acc2(e2x, e2y, a0, b1, -sgn);
+                };
+                {
+                    int p = 0;
+                    for (; p < G.npos; ++p) cross(p, 1.0, 1.0);
+                    for (; p < G.npos + G.nneg; ++p) cross(p, -1.0, 1.0);
+                    for (; p < G.npair; ++p) cross(p, 1.0, (double)G.m[p]);
                 }
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {

@@ -41,6 +41,7 @@ struct BlocksDesc {
 // S_f(x)[3 s3 + ., i3])_r, and Aop_k(x, r)[i1] = S_f(x)[3 alpha_k + r, i1].
 struct NucGroupDev {
     int32_t f, g, npair, nk;
+    int32_t npos, nneg;             // pairs with M = +1 first, then M = -1, then the rest
     int32_t s2[16], s3[16], m[16];  // 32-bit: read with scalar loads
     int32_t alpha[kMaxKindsPerGroup], kind_out[kMaxKindsPerGroup];
 };
