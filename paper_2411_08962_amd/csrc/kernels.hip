@@ -750,7 +750,7 @@ __global__ __launch_bounds__(256) void contract_kernel(const double2 *__restrict
 // Term sum with the blocks of ntg <= kMaxTG consecutive time slices in LDS:
 // each term's word (or plain indices and coefficient) is read once and
 // evaluated for every staged slice.
-template <int A, bool PACKED>
+template <int A, bool PACKED, bool REAL = false>
 __device__ __forceinline__ void term_sum(const double2 *__restrict__ sB, int KB, int ntg,
                                          const double2 *__restrict__ spal, const TermTable &tab, int64_t N,
                                          int64_t n0, int64_t n1, double (&ar)[kMaxTG], double (&ai)[kMaxTG])
@@ -766,8 +766,13 @@ __device__ __forceinline__ void term_sum(const double2 *__restrict__ sB, int KB,
                     const double2 b = Bt[idx[a]];
                     p = double2{p.x * b.x - p.y * b.y, p.x * b.y + p.y * b.x};
                 }
-                ar[tg] += cx * p.x - cy * p.y;
-                ai[tg] += cx * p.y + cy * p.x;
+                if constexpr (REAL) {
+                    ar[tg] += cx * p.x;
+                    ai[tg] += cx * p.y;
+                } else {
+                    ar[tg] += cx * p.x - cy * p.y;
+                    ai[tg] += cx * p.y + cy * p.x;
+                }
             }
         }
     };
@@ -934,6 +939,7 @@ __device__ __forceinline__ void reduce_tg(double (&ar)[kMaxTG], double (&ai)[kMa
 
 // One plan: workgroup (group of tg consecutive (cfg, t) sets, table slice);
 // a slice is slice_len terms (plain, packed) or slice_len chunks (segmented).
+// FORM: 0 plain, 1 packed, 2 segmented, 3 packed with a real palette.
 template <int A, int FORM>
 __global__ __launch_bounds__(kCThreads) void contract_tg_kernel(const double2 *__restrict__ B, TermTable tab,
                                                                 int64_t N, int K, int n_ct, int tg, int n_slices,
@@ -957,7 +963,7 @@ __global__ __launch_bounds__(kCThreads) void contract_tg_kernel(const double2 *_
     } else {
         const int64_t n0 = (int64_t)slice * slice_len;
         const int64_t n1 = n0 + slice_len < N ? n0 + slice_len : N;
-        term_sum<A, FORM == 1>(sB, KB, ntg, spal, tab, N, n0, n1, ar, ai);
+        term_sum<A, FORM == 1 || FORM == 3, FORM == 3>(sB, KB, ntg, spal, tab, N, n0, n1, ar, ai);
     }
     reduce_tg(ar, ai, ntg, red, partial + (int64_t)ct0 * n_slices + slice, n_slices);
 }
@@ -1051,17 +1057,21 @@ __global__ __launch_bounds__(kCThreads) void contract_batch_kernel(const double2
     }
     const int64_t n0 = (int64_t)w.slice * it.slice_len;
     const int64_t n1 = n0 + it.slice_len < it.N ? n0 + it.slice_len : it.N;
-    const bool packed = it.tab.words != nullptr;
-    switch (it.A * 2 + (packed ? 1 : 0)) {
-    case 2: term_sum<1, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
-    case 3: term_sum<1, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
-    case 4: term_sum<2, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
-    case 5: term_sum<2, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
-    case 6: term_sum<3, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
-    case 7: term_sum<3, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
-    case 8: term_sum<4, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
-    case 9: term_sum<4, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
-    case 10: term_sum<5, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    const int form = it.tab.words ? (it.tab.coef_real ? 3 : 1) : 0;
+    switch (it.A * 4 + form) {
+    case 4: term_sum<1, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 5: term_sum<1, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 7: term_sum<1, true, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 8: term_sum<2, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 9: term_sum<2, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 11: term_sum<2, true, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 12: term_sum<3, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 13: term_sum<3, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 15: term_sum<3, true, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 16: term_sum<4, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 17: term_sum<4, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 19: term_sum<4, true, true>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
+    case 20: term_sum<5, false>(sB, KB, ntg, spal, it.tab, it.N, n0, n1, ar, ai); break;
     default: break;
     }
     reduce_tg(ar, ai, ntg, red, partial + it.part_off + (int64_t)w.t0 * it.n_slices + w.slice, it.n_slices);
@@ -1201,21 +1211,25 @@ hipError_t launch_contract(const ContractLaunch &L, hipStream_t s)
         if (L.tg > kMaxTG || L.tg * L.K > kMaxLdsKinds) return hipErrorInvalidValue;
         const int64_t n_groups = (L.n_ct + L.tg - 1) / L.tg;
         const unsigned blocks = (unsigned)round8(n_groups * L.n_slices);
-        const int form = L.tab.seg_prefix ? 2 : (L.tab.words ? 1 : 0);
+        const int form = L.tab.seg_prefix ? 2 : (L.tab.words ? (L.tab.coef_real ? 3 : 1) : 0);
         hipError_t e = hipErrorInvalidValue;
-        switch (L.A * 3 + form) {
-        case 3: e = launch_tg<1, 0>(L, s, blocks); break;
-        case 4: e = launch_tg<1, 1>(L, s, blocks); break;
-        case 6: e = launch_tg<2, 0>(L, s, blocks); break;
-        case 7: e = launch_tg<2, 1>(L, s, blocks); break;
-        case 8: e = launch_tg<2, 2>(L, s, blocks); break;
-        case 9: e = launch_tg<3, 0>(L, s, blocks); break;
-        case 10: e = launch_tg<3, 1>(L, s, blocks); break;
-        case 11: e = launch_tg<3, 2>(L, s, blocks); break;
-        case 12: e = launch_tg<4, 0>(L, s, blocks); break;
-        case 13: e = launch_tg<4, 1>(L, s, blocks); break;
-        case 14: e = launch_tg<4, 2>(L, s, blocks); break;
-        case 15: e = launch_tg<5, 0>(L, s, blocks); break;
+        switch (L.A * 4 + form) {
+        case 4: e = launch_tg<1, 0>(L, s, blocks); break;
+        case 5: e = launch_tg<1, 1>(L, s, blocks); break;
+        case 7: e = launch_tg<1, 3>(L, s, blocks); break;
+        case 8: e = launch_tg<2, 0>(L, s, blocks); break;
+        case 9: e = launch_tg<2, 1>(L, s, blocks); break;
+        case 10: e = launch_tg<2, 2>(L, s, blocks); break;
+        case 11: e = launch_tg<2, 3>(L, s, blocks); break;
+        case 12: e = launch_tg<3, 0>(L, s, blocks); break;
+        case 13: e = launch_tg<3, 1>(L, s, blocks); break;
+        case 14: e = launch_tg<3, 2>(L, s, blocks); break;
+        case 15: e = launch_tg<3, 3>(L, s, blocks); break;
+        case 16: e = launch_tg<4, 0>(L, s, blocks); break;
+        case 17: e = launch_tg<4, 1>(L, s, blocks); break;
+        case 18: e = launch_tg<4, 2>(L, s, blocks); break;
+        case 19: e = launch_tg<4, 3>(L, s, blocks); break;
+        case 20: e = launch_tg<5, 0>(L, s, blocks); break;
         default: break;
         }
         if (e != hipSuccess) return e;

@@ -313,3 +313,22 @@ def test_proton_single_nucleon_table():
         hu, hd, du, dd = props(15, 1, (2, 2, 2, 3))
         C = w.contract(pl, w.blocks(pl, du, dd)).cpu().numpy()
         check_C(ops.proton(a), pl, C, hu, hd, range(3))
+
+
+def test_complex_pattern_coefficients():
+    """Complex sink and source couplings give a complex coefficient palette
+    (the packed term sum's complex branch), single and batched."""
+    w = W()
+    op = ops.deuteron()
+    snk = [(k, (c[0] * 1 - c[1] * 2, c[0] * 2 + c[1] * 1)) for k, c in op.snk]    # x (1 + 2i)
+    src = [(k, (c[0] * 2 + c[1] * 1, -c[0] * 1 + c[1] * 2)) for k, c in op.src]    # x (2 - i)
+    opc = ops.Operator(op.A, op.kinds, snk, src, op.scale, "2H-complex")
+    from tests.helpers import to_wick
+    pl = w.plan(**to_wick(opc))
+    kidx, coef = pl.table()
+    assert np.any(coef.imag != 0)
+    hu, hd, du, dd = props(16, 1, (3, 2, 2, 3))
+    C = w.contract(pl, w.blocks(pl, du, dd)).cpu().numpy()
+    check_C(opc, pl, C, hu, hd, range(3))
+    Cb = w.correlator([pl], [(0, 0)], du, dd).cpu().numpy()
+    check_C(opc, pl, Cb, hu, hd, range(3))

@@ -298,3 +298,15 @@ def test_autotune_rejects_bad_arguments_and_corrupt_cache(tmp_path):
     with pytest.raises(W.WickError) as e:
         W.autotune(pl, (4, 4, 4, 8), cache_path=bad)
     assert e.value.status == W.ECORRUPT
+
+
+def test_complex_coefficient_plan_matches_oracle():
+    op = ops.deuteron()
+    snk = [(k, (c[0] - 2 * c[1], 2 * c[0] + c[1])) for k, c in op.snk]
+    src = [(k, (2 * c[0] + c[1], -c[0] + 2 * c[1])) for k, c in op.src]
+    opc = ops.Operator(op.A, op.kinds, snk, src, op.scale, "2H-complex")
+    pl = W.plan(**to_wick(opc))
+    got, mag = check_plan(opc, pl, *small())
+    # the complex couplings multiply C by (1 + 2i)(2 - i) = 4 + 3i
+    ref, _ = check_plan(op, W.plan_std("2H"), *small())
+    assert abs(got - (4 + 3j) * ref) <= 1e-12 * 5 * mag
