@@ -43,18 +43,19 @@ DEFAULT = "3He-16^3x32"
 PEAK_TFLOPS = {"p64": 78.6, "p32": 157.3, "pb3": 2500.0, "pb6": 2500.0}
 PEAK_NAME = {"p64": "FP64 MFMA", "p32": "FP32 MFMA", "pb3": "BF16 MFMA", "pb6": "BF16 MFMA"}
 
-# executed algorithmic flops per site of the nucleon-form block kernel:
-# (kinds per group, nonzero diquark-matrix entries per group)
-GROUPS = {"2H": [(2, 4), (2, 4)], "3He": [(4, 2), (1, 2), (4, 2)], "3H": [(4, 2), (1, 2), (4, 2)],
-          "4He": [(2, 4), (2, 4)]}
+# algorithmic flops per site of the nucleon-form block build: block kinds per
+# nucleus, and the distinct E-row sets (nonzero diquark-matrix entries of each;
+# a p group and its n twin with an antisymmetric diquark matrix share one)
+KINDS = {"2H": 4, "3He": 9, "3H": 9, "4He": 4}
+EROWS = {"2H": [4], "3He": [2, 2], "3H": [2, 2], "4He": [4]}
 
 
 def block_flops_per_site(nucleus):
     """GEMM: 12 rows (i1) per kind x 144 columns x 3 E rows x 8 flops per complex
     multiply-add; E rows: per nonzero diquark entry 6 complex products and
     adds for the three colour cross products (8 flops each) per column."""
-    gemm = sum(12 * nk * 144 * 3 * 8 for nk, _ in GROUPS[nucleus])
-    erow = sum(144 * npair * 6 * 8 for _, npair in GROUPS[nucleus])
+    gemm = 12 * KINDS[nucleus] * 144 * 3 * 8
+    erow = sum(144 * npair * 6 * 8 for npair in EROWS[nucleus])
     return gemm + erow
 
 

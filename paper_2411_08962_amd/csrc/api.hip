@@ -366,27 +366,62 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
     // the nucleon kernel's descriptors: groups packed into passes of at most
     // 4 m-tiles (FP64) or 3 (split modes, which also hold FP32 accumulators)
     if (!p->nucgroups.empty() && p->nucgroups.size() <= (size_t)kMaxGroupsStaged) {
+        // twin groups (see NucGroupDev) share one E; WICK_NO_TWINS=1 keeps them apart (testing)
+        auto twins = [&](const NucGroup &a, const NucGroup &b) {
+            if (b.f != a.g || b.g != a.f || a.pairs.size() != b.pairs.size()) return false;
+            for (const auto &x : a.pairs) {
+                bool found = false;
+                for (const auto &y : b.pairs) found |= y[0] == x[1] && y[1] == x[0] && y[2] == -x[2];
+                if (!found) return false;
+            }
+            return true;
+        };
+        const bool no_twins = std::getenv("WICK_NO_TWINS") != nullptr;
+        struct DevGroup {
+            const NucGroup *own;
+            std::vector<std::array<int, 4>> kinds;  // kind_out, alpha, flv, tr
+        };
         for (int which = 0; which < 2; ++which) {
             const int cap = which == 0 ? 4 : 3;
+            const int G0 = (int)p->nucgroups.size();
+            std::vector<DevGroup> dgs;
+            std::vector<char> used(G0, 0);
+            for (int a = 0; a < G0; ++a) {
+                if (used[a]) continue;
+                used[a] = 1;
+                const NucGroup &na = p->nucgroups[a];
+                DevGroup dg{&na, {}};
+                for (size_t k = 0; k < na.kinds.size(); ++k) dg.kinds.push_back({na.kinds[k], na.alpha[k], 0, 0});
+                for (int b = a + 1; b < G0 && !no_twins; ++b) {
+                    const NucGroup &nb = p->nucgroups[b];
+                    const size_t nk = na.kinds.size() + nb.kinds.size();
+                    if (used[b] || nk > (size_t)kMaxKindsPerGroup || (int)(12 * nk + 15) / 16 > cap || !twins(na, nb))
+                        continue;
+                    used[b] = 1;
+                    for (size_t k = 0; k < nb.kinds.size(); ++k) dg.kinds.push_back({nb.kinds[k], nb.alpha[k], 1, 1});
+                    break;
+                }
+                dgs.push_back(dg);
+            }
             NucDesc nd;
             std::memset(&nd, 0, sizeof(nd));
             for (int pp = 0; pp < kMaxPasses; ++pp)
                 for (int t = 0; t < kPassTiles; ++t) nd.tile_group[pp][t] = -1;
             bool ok = true;
             int maxt = 0;
-            const int G = (int)p->nucgroups.size();
+            const int G = (int)dgs.size();
             std::vector<int> order(G);
             for (int g = 0; g < G; ++g) order[g] = g;
-            auto tiles_of = [&](int g) { return (12 * (int)p->nucgroups[g].kinds.size() + 15) / 16; };
+            auto tiles_of = [&](int g) { return (12 * (int)dgs[g].kinds.size() + 15) / 16; };
             std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tiles_of(x) > tiles_of(y); });
             nd.n_groups = G;
             for (int g : order) {
-                const NucGroup &ng = p->nucgroups[g];
+                const NucGroup &ng = *dgs[g].own;
                 NucGroupDev &h = nd.groups[g];
                 h.f = ng.f;
                 h.g = ng.g;
                 h.npair = (int)ng.pairs.size();
-                h.nk = (int)ng.kinds.size();
+                h.nk = (int)dgs[g].kinds.size();
                 // diquark entries ordered M = +1, M = -1, other values (the kernel
                 // folds a unit M into the sign pattern of its FMA chains)
                 std::vector<std::array<int8_t, 3>> pr(ng.pairs.begin(), ng.pairs.end());
@@ -401,8 +436,10 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
                     h.nneg += pr[i][2] == -1;
                 }
                 for (int k = 0; k < h.nk; ++k) {
-                    h.alpha[k] = ng.alpha[k];
-                    h.kind_out[k] = ng.kinds[k];
+                    h.kind_out[k] = dgs[g].kinds[k][0];
+                    h.alpha[k] = dgs[g].kinds[k][1];
+                    h.flv[k] = dgs[g].kinds[k][2];
+                    h.tr[k] = dgs[g].kinds[k][3];
                 }
                 const int mt = tiles_of(g);
                 int pp = 0;

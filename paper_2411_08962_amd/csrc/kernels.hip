@@ -406,7 +406,8 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
             const CNucGroup &G = desc->groups[g];
             const int m = desc->tile_mt[pass][t] * 16 + c;
             const int kk = m / 12 < G.nk ? m / 12 : G.nk - 1;
-            bo[t] = 36 * G.alpha[kk] + m % 12;
+            // a twin kind reads its row from S_g: the other flavor's staging area
+            bo[t] = (G.flv[kk] ? (G.g - G.f) * kNucSites * 144 : 0) + 36 * G.alpha[kk] + m % 12;
         }
     }
     d4 acc[NT][2];
@@ -660,12 +661,14 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
         const CNucGroup &G = desc->groups[tgroup[t]];
         const int m = desc->tile_mt[pass][t] * 16 + c, kk = m / 12, i1 = m % 12;
         if (kk >= G.nk) continue;
-        double2 *row = P + ((int64_t)G.kind_out[kk] * 12 + i1) * 144 + nt * 16;
-        // f64 MFMA result: row 4*v + q; f32 / bf16 MFMA result: row 4*q + v
+        double2 *row = P + ((int64_t)G.kind_out[kk] * 12 + i1) * 144;
+        const bool tr = G.tr[kk] != 0;
+        // f64 MFMA result: column 4*v + q of the tile; f32 / bf16 MFMA result: 4*q + v.
+        // A twin kind's column (i2, i3) is (i3, i2) of its own block.
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int rr = kSplit ? 4 * q + v : 4 * v + q;
-            row[rr] = double2{acc[t][0][v], acc[t][1][v]};
+            const int col = nt * 16 + (kSplit ? 4 * q + v : 4 * v + q);
+            row[tr ? (col % 12) * 12 + col / 12 : col] = double2{acc[t][0][v], acc[t][1][v]};
         }
     }
 }

@@ -39,11 +39,19 @@ struct BlocksDesc {
 // Nucleon-form groups (see NucGroup): E_r(x)[i2,i3] = sum over the nonzero
 // M[s3][s2] of M * (colour cross product of S_g(x)[3 s2 + ., i2] and
 // S_f(x)[3 s3 + ., i3])_r, and Aop_k(x, r)[i1] = S_f(x)[3 alpha_k + r, i1].
+//
+// A group may also carry the kinds of its twin: the group with flavors (g, f)
+// and diquark entries (s3, s2, -M) for every (s2, s3, M) of this one, whose
+// rows are E_r(x)[i3, i2] of this group's E_r(x)[i2, i3] (swap the two
+// propagators in the colour cross product and relabel the spins). A twin
+// kind reads its Aop row from S_g (flv = 1) and stores its columns
+// transposed (tr = 1), so one E serves both groups.
 struct NucGroupDev {
     int32_t f, g, npair, nk;
     int32_t npos, nneg;             // pairs with M = +1 first, then M = -1, then the rest
     int32_t s2[16], s3[16], m[16];  // 32-bit: read with scalar loads
     int32_t alpha[kMaxKindsPerGroup], kind_out[kMaxKindsPerGroup];
+    int32_t flv[kMaxKindsPerGroup], tr[kMaxKindsPerGroup];
 };
 struct NucDesc {
     int32_t n_groups, n_passes;

@@ -332,3 +332,23 @@ def test_complex_pattern_coefficients():
     check_C(opc, pl, C, hu, hd, range(3))
     Cb = w.correlator([pl], [(0, 0)], du, dd).cpu().numpy()
     check_C(opc, pl, Cb, hu, hd, range(3))
+
+
+@pytest.mark.parametrize("twins", ["merged", "separate"])
+@pytest.mark.parametrize("name,dims", [("2H", (3, 2, 2, 2)), ("3He", (3, 1, 1, 2)), ("4He", (2, 1, 1, 1))])
+def test_twin_groups(monkeypatch, twins, name, dims):
+    """Groups whose E rows are each other's transposes (p and n kinds with an
+    antisymmetric diquark matrix) share one E computation; with and without
+    the merge, every precision matches the oracle."""
+    if twins == "separate":
+        monkeypatch.setenv("WICK_NO_TWINS", "1")
+    w = W()
+    pl = w.plan_std(name)  # a fresh plan: its device descriptor is built under this setting
+    hu, hd, du, dd = props(17, 1, dims)
+    for prec in ("p64", "p32"):
+        B = w.blocks(pl, du, dd, prec).cpu().numpy()
+        if prec == "p64":
+            check_blocks(ops.by_name(name), pl, B, hu, hd, range(dims[3]))
+        C = w.contract(pl, w.blocks(pl, du, dd, prec)).cpu().numpy()
+        check_C(ops.by_name(name), pl, C, hu, hd, range(dims[3]), tol=TOL64 if prec == "p64" else SPLIT_TOL[prec])
+
