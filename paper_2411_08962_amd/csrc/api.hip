@@ -847,8 +847,9 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
         c.K = K;
         c.tg = slices_per_group(K, T);
         cpart += (int64_t)T * c.n_slices;
-        for (int t0 = 0; t0 < T; t0 += c.tg)
-            for (int sl = 0; sl < c.n_slices; ++sl) cw.push_back({i, t0, sl, std::min(c.tg, T - t0)});
+        // slice-major (see contract_tg_kernel): one slice's workgroups are adjacent
+        for (int sl = 0; sl < c.n_slices; ++sl)
+            for (int t0 = 0; t0 < T; t0 += c.tg) cw.push_back({i, t0, sl, std::min(c.tg, T - t0)});
     }
     bout[n_items] = bo;
     if (bw.size() > 0x7ffffff0ULL || cw.size() > 0x7ffffff0ULL) return fail(WICK_ETOOBIG, "batch too large");

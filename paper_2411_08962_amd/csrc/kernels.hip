@@ -958,6 +958,9 @@ __global__ __launch_bounds__(kCThreads) void contract_tg_kernel(const double2 *_
     const int n_groups = (n_ct + tg - 1) / tg;
     const int lb = xcd_block();
     if (lb >= n_groups * n_slices) return;
+    // group-major: adjacent workgroups share their staged blocks (measured
+    // faster than slice-major for one plan; the batched path orders its work
+    // list slice-major, measured faster there)
     const int g = lb / n_slices, slice = lb % n_slices;
     const int ct0 = g * tg, ntg = n_ct - ct0 < tg ? n_ct - ct0 : tg;
     const int KB = K * 792;
