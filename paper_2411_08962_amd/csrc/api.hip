@@ -215,7 +215,7 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
     for (size_t c = 0; c < n_chunks; ++c) {
         out.base[c] = (int64_t)total;
         out.len[c] = (int32_t)segs[c * 64].second;  // nodes per lane
-        total += (size_t)out.len[c] * kNodeLeaves * 64;
+        total += (size_t)out.len[c] * 64;  // one word per node
     }
     out.words.assign(total, 0);  // zero word: leaf 0, node 0, palette entry 0 (zero)
     for (size_t c = 0; c < n_chunks; ++c)
@@ -227,12 +227,14 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
             out.prefix[si] = prefix_of(ord[nodes[n0].first]);
             for (uint32_t kk = 0; kk < nn; ++kk) {
                 const auto &nd = nodes[n0 + kk];
-                for (int l = 0; l < nd.second; ++l) {
-                    const uint32_t t = ord[nd.first + l];
-                    w[((size_t)kk * kNodeLeaves + l) * 64] = (uint64_t)ix(A - 1, t) |
-                                                             ((uint64_t)ix(A - 2, t) << kPackBits) |
-                                                             ((uint64_t)pidx[t] << (2 * kPackBits));
+                const uint32_t t0 = ord[nd.first];
+                uint64_t v = (uint64_t)ix(A - 1, t0) | ((uint64_t)ix(A - 2, t0) << kPackBits) |
+                             ((uint64_t)pidx[t0] << (2 * kPackBits));
+                if (nd.second > 1) {
+                    const uint32_t t1 = ord[nd.first + 1];
+                    v |= ((uint64_t)ix(A - 1, t1) << 36) | ((uint64_t)pidx[t1] << 50);
                 }
+                w[(size_t)kk * 64] = v;
             }
         }
     return true;

@@ -828,7 +828,7 @@ __device__ __forceinline__ void term_sum_seg(const double2 *__restrict__ sB, int
                                              double (&ar)[kMaxTG], double (&ai)[kMaxTG])
 {
     constexpr uint32_t kMask = (1u << kPackBits) - 1;
-    constexpr int U = kPrefetch / kNodeLeaves;  // nodes in flight
+    static_assert(kNodeLeaves == 2, "one 64-bit word per node holds two leaves");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int c = c0 + wave; c < c1; c += kCThreads / 64) {
         const uint32_t pre = tab.seg_prefix[(int64_t)c * 64 + lane];
@@ -850,38 +850,34 @@ __device__ __forceinline__ void term_sum_seg(const double2 *__restrict__ sB, int
         }
         const uint64_t *wp = tab.words + tab.chunk_base[c] + lane;
         const int nodes = tab.chunk_len[c];  // uniform over the wave
-        uint64_t cur[U * kNodeLeaves], nxt[U * kNodeLeaves] = {};
-        auto fetch = [&](int k0, uint64_t (&w)[U * kNodeLeaves]) {
+        uint64_t cur[kPrefetch], nxt[kPrefetch] = {};
+        auto fetch = [&](int k0, uint64_t (&w)[kPrefetch]) {
 #pragma unroll
-            for (int u = 0; u < U * kNodeLeaves; ++u)
-                w[u] = k0 + u / kNodeLeaves < nodes ? wp[((int64_t)k0 * kNodeLeaves + u) * 64] : 0;
+            for (int u = 0; u < kPrefetch; ++u) w[u] = k0 + u < nodes ? wp[(int64_t)(k0 + u) * 64] : 0;
         };
         fetch(0, cur);
-        for (int k0 = 0; k0 < nodes; k0 += U) {
-            if (k0 + U < nodes) fetch(k0 + U, nxt);
+        for (int k0 = 0; k0 < nodes; k0 += kPrefetch) {
+            if (k0 + kPrefetch < nodes) fetch(k0 + kPrefetch, nxt);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < kPrefetch; ++u) {
                 if (k0 + u < nodes) {
-                    const int in = (int)((cur[u * kNodeLeaves] >> kPackBits) & kMask);
+                    const uint64_t w = cur[u];
+                    const int in = (int)((w >> kPackBits) & kMask);
+                    const int l0 = (int)(w & kMask), l1 = (int)((w >> 36) & kMask);
+                    const double2 c0v = spal[(int)(w >> 28) & 0xff], c1v = spal[(int)(w >> 50) & 0xff];
 #pragma unroll
                     for (int tg = 0; tg < kMaxTG; ++tg) {
                         if (tg < ntg) {
                             const double2 *Bt = sB + tg * KB;
-                            double s3x = 0.0, s3y = 0.0;
-#pragma unroll
-                            for (int l = 0; l < kNodeLeaves; ++l) {
-                                const uint64_t w = cur[u * kNodeLeaves + l];
-                                const double2 cf = spal[(int)(w >> (2 * kPackBits)) & 0xff];
-                                const double2 b = Bt[(int)(w & kMask)];
-                                if constexpr (REAL) {
-                                    s3x = fma(cf.x, b.x, s3x);
-                                    s3y = fma(cf.x, b.y, s3y);
-                                } else {
-                                    s3x += cf.x * b.x - cf.y * b.y;
-                                    s3y += cf.x * b.y + cf.y * b.x;
-                                }
+                            const double2 b0 = Bt[l0], b1 = Bt[l1], bn = Bt[in];
+                            double s3x, s3y;
+                            if constexpr (REAL) {
+                                s3x = fma(c1v.x, b1.x, c0v.x * b0.x);
+                                s3y = fma(c1v.x, b1.y, c0v.x * b0.y);
+                            } else {
+                                s3x = c0v.x * b0.x - c0v.y * b0.y + c1v.x * b1.x - c1v.y * b1.y;
+                                s3y = c0v.x * b0.y + c0v.y * b0.x + c1v.x * b1.y + c1v.y * b1.x;
                             }
-                            const double2 bn = Bt[in];
                             sx[tg] += bn.x * s3x - bn.y * s3y;
                             sy[tg] += bn.x * s3y + bn.y * s3x;
                         }
@@ -889,7 +885,7 @@ __device__ __forceinline__ void term_sum_seg(const double2 *__restrict__ sB, int
                 }
             }
 #pragma unroll
-            for (int u = 0; u < U * kNodeLeaves; ++u) cur[u] = nxt[u];
+            for (int u = 0; u < kPrefetch; ++u) cur[u] = nxt[u];
         }
 #pragma unroll
         for (int tg = 0; tg < kMaxTG; ++tg) {

@@ -85,17 +85,18 @@ constexpr int kMaxPalette = 256;
 // Segmented form (2 <= A <= 4, K <= 12, at most 255 distinct coefficients),
 // which shares the leading indices of the terms. The table sorted by index
 // tuple is cut into nodes (terms sharing their first A-1 indices, at most
-// kNodeLeaves of them, padded with zero-coefficient terms) and segments (at
-// most seg_len / kNodeLeaves consecutive nodes sharing the first A-2
+// kNodeLeaves = 2 of them, padded with a zero-coefficient term) and segments
+// (at most seg_len / kNodeLeaves consecutive nodes sharing the first A-2
 // indices, the segment prefix). A lane evaluates one segment as
 //   P * sum_nodes B[node] * sum_leaves coef * B[leaf],   P = prod of the prefix entries,
 // so every term costs one LDS gather and every node one more, instead of A
-// per term; as every node has the same number of words the lanes of a wave
-// never diverge. Segments are sorted by length and dealt to the 64 lanes of
-// a chunk; chunk c holds chunk_len[c] nodes per lane, interleaved (word j of
-// lane l at chunk_base[c] + 64 j + l), shorter segments padded with zero
-// words. Word bits: leaf index [0,14), node index [14,28) (read from a
-// node's first word), palette index [28,36); palette entry 0 is zero.
+// per term; as every node is one word the lanes of a wave never diverge.
+// Segments are sorted by length and dealt to the 64 lanes of a chunk; chunk
+// c holds chunk_len[c] nodes per lane, interleaved (node j of lane l at
+// chunk_base[c] + 64 j + l), shorter segments padded with zero words. Node
+// word bits: leaf 0 [0,14), node index [14,28), palette index of leaf 0
+// [28,36), leaf 1 [36,50), palette index of leaf 1 [50,58); palette entry 0
+// is zero.
 constexpr int kNodeLeaves = 2;
 struct TermTable {
     const uint64_t *words;  // packed [N] or segmented (interleaved chunks), or null
