@@ -352,3 +352,75 @@ def test_twin_groups(monkeypatch, twins, name, dims):
         C = w.contract(pl, w.blocks(pl, du, dd, prec)).cpu().numpy()
         check_C(ops.by_name(name), pl, C, hu, hd, range(dims[3]), tol=TOL64 if prec == "p64" else SPLIT_TOL[prec])
 
+
+
+# ------------------------------------------------------------- edge cases
+def _pauli_plan(w):
+    # source quarks repeat a spin-colour index: every Wick term vanishes (empty table)
+    op = ops.deuteron()
+    src_kinds = [(k.flavors, [(j1, j2, j1, a, b) for (j1, j2, j3, a, b) in k.w]) for k in op.kinds]
+    kinds = [(k.flavors, k.w) for k in op.kinds] + src_kinds
+    K = len(op.kinds)
+    src = [(tuple(i + K for i in p), c) for p, c in op.src]
+    return w.plan(A=2, kinds=kinds, snk=op.snk, src=src)
+
+
+def test_empty_table_gives_zero_correlator():
+    torch = _torch()
+    w = W()
+    pe = _pauli_plan(w)
+    assert pe.n_terms == 0
+    _, _, du, dd = props(18, 2, (2, 2, 1, 3))
+    C = torch.full((2, 3, 2), 7.0, dtype=torch.float64, device="cuda")
+    w.contract(pe, w.blocks(pe, du, dd), out=C)
+    assert np.all(C.cpu().numpy() == 0)
+    # in a batch beside a nonempty plan, also as a replayed graph
+    p2 = w.plan_std("2H")
+    for graph in (False, True):
+        Cb = w.correlator([pe, p2], [(0, 0), (1, 1), (0, 1)], du, dd, use_graph=graph).cpu().numpy()
+        assert np.all(Cb[0] == 0) and np.all(Cb[2] == 0) and np.any(Cb[1] != 0)
+
+
+def test_single_site_single_slice_and_zero_propagators():
+    torch = _torch()
+    w = W()
+    pl = w.plan_std("3He")
+    hu, hd, du, dd = props(19, 1, (1, 1, 1, 1))
+    C = w.contract(pl, w.blocks(pl, du, dd)).cpu().numpy()
+    check_C(ops.helium3(), pl, C, hu, hd, [0])
+    z = torch.zeros_like(du)
+    for prec in ("p64", "p32", "pb3", "pb6"):
+        Cz = w.contract(pl, w.blocks(pl, z, z, prec)).cpu().numpy()
+        assert np.all(Cz == 0), prec
+
+
+def test_ragged_volumes_across_chunk_and_batch_boundaries():
+    # volumes that are not multiples of the 16-site batch, the 4-site MFMA
+    # step or the tuned chunk, in both the single and the batched launch
+    w = W()
+    pl = w.plan_std("2H")
+    for dims in ((17, 1, 1, 2), (5, 7, 3, 1), (33, 2, 1, 1)):
+        hu, hd, du, dd = props(20, 1, dims)
+        for prec in ("p64", "pb6"):
+            tol = TOL64 if prec == "p64" else SPLIT_TOL[prec]
+            C = w.contract(pl, w.blocks(pl, du, dd, prec)).cpu().numpy()
+            check_C(ops.deuteron(), pl, C, hu, hd, range(dims[3]), tol=tol)
+            Cb = w.correlator([pl], [(0, 0)], du, dd, prec).cpu().numpy()
+            check_C(ops.deuteron(), pl, Cb, hu, hd, range(dims[3]), tol=tol)
+
+
+def test_argument_errors_are_reported():
+    torch = _torch()
+    w = W()
+    pl = w.plan_std("2H")
+    _, _, du, dd = props(21, 1, (2, 2, 2, 2))
+    with pytest.raises(ValueError):
+        w.blocks(pl, du, dd[:, :1].contiguous())        # shapes differ
+    with pytest.raises(ValueError):
+        w.blocks(pl, du, dd, out=torch.empty(3, device="cuda", dtype=torch.float64))
+    with pytest.raises(w.WickError) as e:
+        w.correlator([pl], [(0, 5)], du, dd)             # configuration out of range
+    assert e.value.status == w.EINVAL
+    with pytest.raises(w.WickError) as e:
+        w.correlator([pl], [(1, 0)], du, dd)             # plan index out of range
+    assert e.value.status == w.EINVAL
