@@ -331,7 +331,32 @@ def cpu_baseline(items, nuclei, hu, hd, plans, C_gpu):
             "sample": f"{len(done)} (nucleus, configuration, time slice) triples of the same workload, first "
                       f"{done[:4]}: oracle blocks (direct sums) + subset-DP term sum; value = table terms "
                       f"covered per second",
-            "seconds": dt, "gpu_vs_oracle_max_rel_diff_of_C": float(max(diffs))}
+            "seconds": dt, "gpu_vs_oracle_max_rel_diff_of_C": float(max(diffs)),
+            "same_table_numpy": same_table_cpu(plans[items[0][0]])}
+
+
+def same_table_cpu(pl):
+    """The deduplicated table itself evaluated on the host with numpy (gather,
+    product, sum; one thread), on random blocks of the plan's shape: the
+    method on the CPU, beside the oracle's own route."""
+    kidx, coef = pl.table()
+    if kidx.shape[1] == 0:
+        return None
+    rng = np.random.default_rng(0)
+    flat = (rng.standard_normal(pl.n_kinds * 792) + 1j * rng.standard_normal(pl.n_kinds * 792))
+    idx = [k.astype(np.int64) for k in kidx]
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        prod = coef * flat[idx[0]]
+        for a in range(1, len(idx)):
+            prod *= flat[idx[a]]
+        prod.sum()
+        reps += 1
+        if time.perf_counter() - t0 > 3.0:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": reps * kidx.shape[1] / dt, "unit": "Wick terms/s", "threads": 1,
+            "sample": f"{reps} evaluation(s) of the {kidx.shape[1]}-term table"}
 
 
 if __name__ == "__main__":
