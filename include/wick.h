@@ -144,6 +144,30 @@ wick_status wick_plan_save(wick_plan_t plan, const char *path);
 wick_status wick_plan_load(const char *path, wick_plan_t *out);
 void wick_plan_destroy(wick_plan_t plan);
 
+/* Important-term truncation (Sec. 5 "distributions of terms in determinants
+ * and blocks", App. D): the few terms with large values carry the correlator
+ * and which terms they are is fixed by the operator, so they can be chosen
+ * once from blocks of a small calibration lattice (even a single site) and
+ * reused on any ensemble with the same kernels.
+ *   B_cal: host double [n_slices][n_kinds][792][2], blocks as written by
+ *          wick_blocks (any calibration configurations and time slices,
+ *          e.g. [n_cfg][T] flattened); n_slices >= 1.
+ *   keep_fraction in (0, 1]: the new plan keeps
+ *          M = clamp(ceil(keep_fraction * N - 1e-6), 1, N) of the N terms.
+ * Ranking: term n has value v_n(s) = coef_n prod_a B_cal[s][kidx_{a,n}] on
+ * slice s; with m_s = max_n |v_n(s)|, its score is the largest
+ * |v_n(s)| / m_s over the slices with m_s > 0. The M highest scores are kept
+ * (equal scores in table order) and stay in table order, with their
+ * coefficients unchanged. If dropped is not NULL it receives, per slice
+ * (host double [n_slices]), the sum of |v_n(s)| over the dropped terms: a
+ * bound on |C_full(s) - C_kept(s)| on the calibration slices.
+ * *out is a new plan (destroy it with wick_plan_destroy); the input plan is
+ * not changed. Blocking, host only. Errors: WICK_EINVAL (null pointers,
+ * n_slices < 1, keep_fraction outside (0, 1] or NaN, non-finite blocks),
+ * WICK_ENOMEM. */
+wick_status wick_plan_truncate(wick_plan_t plan, const double *B_cal, int32_t n_slices,
+                               double keep_fraction, wick_plan_t *out, double *dropped);
+
 /* ------------------------------------------------------------ GPU compute */
 
 /* Baryon blocks of every kind of the plan on every configuration and time

@@ -13,6 +13,10 @@ Routes to C(t) for one time slice (all FP64, compensated accumulation):
   every flavor-preserving bijection with its sign (Eq. 2.6 / App. D).
 * ``sum_dp``: blocks, the source antisymmetrised first (method A, Sec. 3.3),
   then a dynamic programme over used source positions.
+* ``term_list`` / ``merged_terms``: the block-form terms themselves (one per
+  canonical slot assignment, then merged by monomial), the objects that the
+  important-term study of Sec. 5 and App. D ranks; ``important_terms`` is that
+  selection written out.
 
 The sign of a bijection is its sign as a permutation of quark positions, so
 the flavor-grouping factor eta of Eq. 2.8 is part of every term; the overall
@@ -63,6 +67,8 @@ def lib():
         L.oracle_source_group_count.argtypes = [i32] + kinds + [i32, P, P, i32]
         L.oracle_source_group_count.restype = ctypes.c_long
         L.oracle_threads.restype = ctypes.c_int32
+        L.oracle_term_list.argtypes = [i32] + kinds + pats + [P, P]
+        L.oracle_term_list.restype = ctypes.c_long
         _lib = L
     return _lib
 
@@ -195,3 +201,74 @@ def correlator(op, Su, Sd, route="dp", t_slices=None):
             c = sum_full(op, B) if route == "full" else sum_dp(op, B)
         out[n] = op.scale * c
     return out
+
+
+# ------------------------------------------------------- block-form terms
+def term_list(op):
+    """Unmerged block-form terms: (ent [n, A] int32, coef [n] complex128, unscaled).
+
+    ent[:, a] = kind * 1728 + i1 * 144 + i2 * 12 + i3 with i1 < i3: the entry of
+    the Eq. 2.4 block (``block_eq24``) of nucleon a, in sink order.
+    """
+    pk = _Packed(op)
+    n = int(lib().oracle_term_list(op.A, *pk.kinds_args(), *pk.pat_args(), None, None))
+    ent = np.zeros((max(n, 1), op.A), dtype=np.int32)
+    coef = np.zeros((max(n, 1), 2), dtype=np.float64)
+    m = int(lib().oracle_term_list(op.A, *pk.kinds_args(), *pk.pat_args(), _p(ent), _p(coef)))
+    assert m == n
+    return ent[:n], coef[:n, 0] + 1j * coef[:n, 1]
+
+
+def merged_terms(op):
+    """Terms with equal monomials merged exactly: (keys [m, A] int32, each row
+    ascending, rows in lexicographic order; coef [m] complex128, scale included).
+    Coefficients are sums of integers (exact in FP64); zero sums are dropped."""
+    ent, c = term_list(op)
+    if len(c) == 0:
+        return np.zeros((0, op.A), dtype=np.int32), np.zeros(0, dtype=np.complex128)
+    keys = np.sort(ent, axis=1)
+    uniq, inv = np.unique(keys, axis=0, return_inverse=True)
+    acc = np.zeros(len(uniq), dtype=np.complex128)
+    np.add.at(acc, inv.reshape(-1), c)
+    nz = acc != 0
+    return uniq[nz], op.scale * acc[nz]
+
+
+def term_values(keys, coef, B_eq24):
+    """v[s, n] = coef_n prod_a B_eq24[s].flat[keys[n, a]] for blocks [S, K, 12, 12, 12]."""
+    flat = np.asarray(B_eq24, dtype=np.complex128).reshape(B_eq24.shape[0], -1)
+    v = np.broadcast_to(np.asarray(coef, dtype=np.complex128), (flat.shape[0], len(coef))).copy()
+    for a in range(keys.shape[1]):
+        v = v * flat[:, keys[:, a].astype(np.int64)]
+    return v
+
+
+def keep_count(n_terms, keep):
+    """Number of terms kept at fraction ``keep``: ceil(keep * N) up to 1e-6, at least 1."""
+    if n_terms <= 0:
+        return 0
+    return int(min(n_terms, max(1.0, np.ceil(keep * float(n_terms) - 1e-6))))
+
+
+def important_terms(keys, coef, B_eq24, keep):
+    """Important-term selection (Sec. 5, App. D): terms ranked by |value| on
+    calibration blocks, each slice's values normalised by its largest one.
+
+    Returns (kept mask [n], score [n], dropped [S]) where score_n is the largest
+    |v[s, n]| / max_m |v[s, m]| over slices with a nonzero maximum, the kept
+    terms are the keep_count(n, keep) largest scores (equal scores: lower index
+    first) and dropped[s] is the sum of |v[s, n]| over the terms not kept.
+    """
+    mag = np.abs(term_values(keys, coef, B_eq24))
+    n = mag.shape[1]
+    score = np.zeros(n)
+    for s in range(mag.shape[0]):
+        m = mag[s].max() if n else 0.0
+        if m > 0:
+            score = np.maximum(score, mag[s] / m)
+    M = keep_count(n, keep)
+    order = np.lexsort((np.arange(n), -score))
+    kept = np.zeros(n, dtype=bool)
+    kept[order[:M]] = True
+    dropped = mag[:, ~kept].sum(axis=1)
+    return kept, score, dropped

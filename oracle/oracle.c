@@ -610,6 +610,73 @@ void oracle_sum_dp(int32_t A, const double *B_,
     out[0] = creal(c); out[1] = cimag(c);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Route 4: the list of block-form terms (Eq. 2.6 / App. D with the source    */
+/* antisymmetrised as in method A of Sec. 3.3), one entry per canonical slot  */
+/* assignment, not merged.                                                    */
+/*                                                                            */
+/* For every source group (U, D) and sink pattern s, every flavor-preserving  */
+/* assignment sigma of the canonical positions to the sink slots is a term    */
+/* c_s * W'(U,D) * sgn(sigma) * prod_a Braw_{k_a}[i1, i2, i3]. The assignment */
+/* that swaps a nucleon's two same-flavor slots has the opposite sign, so the */
+/* 2^A assignments of one class add up to one product of blocks of Eq. 2.4,   */
+/* Beq[i1,i2,i3] = Braw[i1,i2,i3] - Braw[i3,i2,i1], taken at the member with  */
+/* i1 < i3 in every nucleon. That member is emitted: entries                  */
+/* ent[A] = k*1728 + i1*144 + i2*12 + i3 (sink order) and its coefficient.    */
+/* With ent == NULL only the count is returned. Kinds must have the same      */
+/* flavor in slots 1 and 3.                                                   */
+/* ------------------------------------------------------------------------- */
+long oracle_term_list(int32_t A, int32_t K, const int32_t *flav, const int32_t *nw, const int32_t *woff,
+                      const int32_t *wj, const double *wre, const double *wim,
+                      int32_t n_snk, const int32_t *snk_kind, const double *snk_c,
+                      int32_t n_src, const int32_t *src_kind, const double *src_c,
+                      int32_t *ent, double *coef)
+{
+    kinds_t ks = {K, flav, nw, woff, wj, wre, wim};
+    const int n = 3 * A;
+    int f0[48], nu = 0;
+    listing(&ks, A, snk_kind, f0);
+    for (int q = 0; q < n; ++q) nu += f0[q] == 0;
+    grp_t *gr;
+    long ng = source_groups(&ks, A, n_src, src_kind, src_c, nu, &gr);
+    int gcanon[48];
+    for (int p = 0; p < n; ++p) gcanon[p] = p < nu ? 0 : 1;
+    long cnt = 0;
+    for (int s = 0; s < n_snk; ++s) {
+        const int32_t *pk = snk_kind + s * A;
+        int f[48], cu = 0;
+        listing(&ks, A, pk, f);
+        for (int q = 0; q < n; ++q) cu += f[q] == 0;
+        if (cu != nu) continue;
+        int *sig, *sgn;
+        int nsig = bijections(f, gcanon, n, &sig, &sgn);
+        cplx cs = snk_c[2 * s] + I * snk_c[2 * s + 1];
+        for (long gi = 0; gi < ng; ++gi) {
+            int val[48];
+            uint64_t key = gr[gi].key;
+            for (int p = n - 1; p >= 0; --p) { val[p] = key & 15; key >>= 4; }
+            for (int b = 0; b < nsig; ++b) {
+                const int *sg = sig + (long)b * n;
+                int canon = 1;
+                for (int a = 0; a < A && canon; ++a) canon = val[sg[3 * a]] < val[sg[3 * a + 2]];
+                if (!canon) continue;
+                if (ent) {
+                    for (int a = 0; a < A; ++a)
+                        ent[cnt * A + a] = pk[a] * 1728 + val[sg[3 * a]] * 144 + val[sg[3 * a + 1]] * 12 +
+                                           val[sg[3 * a + 2]];
+                    cplx c = cs * gr[gi].w * (double)sgn[b];
+                    coef[2 * cnt] = creal(c);
+                    coef[2 * cnt + 1] = cimag(c);
+                }
+                ++cnt;
+            }
+        }
+        free(sig); free(sgn);
+    }
+    free(gr);
+    return cnt;
+}
+
 /* Number of OpenMP threads the oracle's parallel loops use. */
 int32_t oracle_threads(void)
 {

@@ -1202,6 +1202,12 @@ wick_status wick_plan_save(wick_plan_t p, const char *path) { WICK_TRY(return sa
 
 wick_status wick_plan_load(const char *path, wick_plan_t *out) { WICK_TRY(return load_plan(path, out)); }
 
+wick_status wick_plan_truncate(wick_plan_t p, const double *B_cal, int32_t n_slices, double keep_fraction,
+                               wick_plan_t *out, double *dropped)
+{
+    WICK_TRY(return truncate_plan(p, B_cal, n_slices, keep_fraction, out, dropped));
+}
+
 void wick_plan_destroy(wick_plan_t p)
 {
     if (!p) return;

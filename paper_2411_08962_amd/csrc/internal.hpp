@@ -93,6 +93,11 @@ void factor_kinds(wick_plan_s *p);  // fills p->egroups and p->nucgroups
 wick_status save_plan(const wick_plan_s *p, const char *path);
 wick_status load_plan(const char *path, wick_plan_t *out);
 
+// important-term truncation (truncate.cpp)
+int64_t truncation_count(int64_t n_terms, double keep);
+wick_status truncate_plan(const wick_plan_s *p, const double *B_cal, int32_t n_slices, double keep,
+                          wick_plan_t *out, double *dropped);
+
 // built-in operators (nuclei.cpp)
 wick_status std_plan(const char *name, int32_t J, wick_plan_t *out);
 

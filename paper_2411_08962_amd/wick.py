@@ -48,7 +48,7 @@ class _Item(ctypes.Structure):
 
 
 EXPORTS = ["wick_plan", "wick_plan_std", "wick_plan_info", "wick_plan_stats", "wick_plan_table",
-           "wick_plan_kind", "wick_plan_save", "wick_plan_load", "wick_plan_destroy", "wick_blocks",
+           "wick_plan_kind", "wick_plan_save", "wick_plan_load", "wick_plan_truncate", "wick_plan_destroy", "wick_blocks",
            "wick_contract", "wick_correlator", "wick_autotune", "wick_shutdown", "wick_last_error",
            "wick_version", "wick_profile", "wick_profile_read"]
 
@@ -74,6 +74,7 @@ def lib():
     L.wick_plan_kind.argtypes = [P, i32, P, ctypes.POINTER(i32), P, P, P]
     L.wick_plan_save.argtypes = [P, ctypes.c_char_p]
     L.wick_plan_load.argtypes = [ctypes.c_char_p, pp]
+    L.wick_plan_truncate.argtypes = [P, P, i32, ctypes.c_double, pp, P]
     L.wick_plan_destroy.argtypes = [P]
     L.wick_plan_destroy.restype = None
     L.wick_blocks.argtypes = [P, P, P, st, P, i32, st, P, P]
@@ -86,7 +87,8 @@ def lib():
     L.wick_last_error.restype = ctypes.c_char_p
     L.wick_version.restype = ctypes.c_char_p
     for name in ("wick_plan", "wick_plan_std", "wick_plan_info", "wick_plan_stats", "wick_plan_table",
-                 "wick_plan_kind", "wick_plan_save", "wick_plan_load", "wick_blocks", "wick_contract",
+                 "wick_plan_kind", "wick_plan_save", "wick_plan_load", "wick_plan_truncate", "wick_blocks",
+                 "wick_contract",
                  "wick_correlator", "wick_autotune", "wick_shutdown", "wick_profile", "wick_profile_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -162,6 +164,27 @@ class Plan:
 
     def save(self, path):
         _check(lib().wick_plan_save(self._h, str(path).encode()))
+
+    def truncate(self, B_cal, keep_fraction):
+        """Important-term truncation: a new plan with the terms that dominate on
+        the calibration blocks B_cal ([..., n_kinds, 792, 2] float64 or
+        [..., n_kinds, 792] complex128; numpy or torch, copied to the host),
+        and the per-slice sum of |dropped terms| ([n_slices] float64)."""
+        if hasattr(B_cal, "detach"):
+            B_cal = B_cal.detach().cpu().numpy()
+        B = np.asarray(B_cal)
+        if np.iscomplexobj(B):
+            B = np.stack([B.real, B.imag], axis=-1)
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        K = self.n_kinds
+        if B.ndim < 3 or B.shape[-3:] != (K, BLOCK_LEN, 2):
+            raise ValueError(f"B_cal must end in ({K}, {BLOCK_LEN}, 2)")
+        n_slices = int(np.prod(B.shape[:-3], dtype=np.int64))
+        dropped = np.zeros(max(n_slices, 1), dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().wick_plan_truncate(self._h, B.ctypes.data_as(ctypes.c_void_p), n_slices, float(keep_fraction),
+                                        ctypes.byref(h), dropped.ctypes.data_as(ctypes.c_void_p)))
+        return Plan(h.value), dropped[:n_slices]
 
     @staticmethod
     def load(path):

@@ -76,3 +76,24 @@ def header_symbols():
     txt = open(os.path.join(ROOT, "include", "wick.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(wick_[a-z_]+)\s*\(", txt)))
+
+
+def table_entries(op, pl):
+    """The plan's table with every index in the oracle's encoding: ent [N, A] with
+    ent = oracle_kind * 1728 + i1 * 144 + i2 * 12 + i3 (i1 < i3; the compact index
+    c = pair(i1, i3) * 12 + i2 of the C header decoded), rows in table order, and coef [N]."""
+    kidx, coef = pl.table()
+    order = np.array(plan_kind_order(op, pl), dtype=np.int64)
+    dec = np.zeros(792, dtype=np.int64)
+    for i3 in range(12):
+        for i1 in range(i3):
+            for i2 in range(12):
+                dec[pair_index(i1, i3) * 12 + i2] = i1 * 144 + i2 * 12 + i3
+    k = kidx.astype(np.int64)
+    ent = order[k // 792] * 1728 + dec[k % 792]
+    return ent.T.copy(), coef
+
+
+def row_index(keys):
+    """{tuple(sorted row): position} for a [N, A] key array."""
+    return {tuple(r): i for i, r in enumerate(np.sort(keys, axis=1).tolist())}
