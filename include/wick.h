@@ -212,6 +212,41 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
 wick_status wick_autotune(wick_plan_t plan, const int32_t dims[4], wick_dtype dtype,
                           wick_precision prec, const char *cache_path);
 
+/* ------------------------------------------------------- point sinks */
+
+/* Point-sink correlators by the determinant method (Sec. 3.1 Eq. 2.9,
+ * improved method B of Sec. 3.3, the form of App. A Eq. A1): all quarks of
+ * the sink operator sit at one site x, summed over x,
+ *   C(t) = scale * sum_x sum_{g, h} W_g W'_h det S_u(x,t)[U_g; U'_h] det S_d(x,t)[D_g; D'_h]
+ * where (U_g, D_g) runs over the sink operator's coefficient tensor
+ * antisymmetrised per flavor (sorted sink index lists with the sign of the
+ * sorting, including the flavor-grouping sign) and (U'_h, D'_h) over the
+ * source's, and det S[R; K] is the determinant of the rows R (sink indices)
+ * and columns K (source indices) of the 12x12 propagator at (x, t). The
+ * minimal set of determinants is the set of distinct (row set, column set)
+ * pairs per flavor. Uses the same wick_nucleus_desc as wick_plan (the sink
+ * patterns are read at one point; kinds need not be nucleon-like). Up to 6
+ * quarks of each flavor. */
+typedef struct wick_point_s *wick_point_t;
+wick_status wick_point_plan(const wick_nucleus_desc *desc, wick_point_t *out);
+wick_status wick_point_plan_std(const char *nucleus, int32_t J, wick_point_t *out);
+
+/* Sizes: quarks per flavor, sink and source groups, distinct sink row sets
+ * and source column sets per flavor (the minimal set has n_rows_u * n_cols_u
+ * u determinants and n_rows_d * n_cols_d d determinants per site). */
+wick_status wick_point_info(wick_point_t plan, int32_t *n_u, int32_t *n_d, int64_t *n_sink_groups,
+                            int64_t *n_src_groups, int64_t *n_rows_u, int64_t *n_cols_u,
+                            int64_t *n_rows_d, int64_t *n_cols_d);
+
+/* C[cfg][t] (device double [n_cfg][T][2]) from propagators laid out as for
+ * wick_blocks (device, 16-byte aligned, complex128 or complex64), FP64
+ * arithmetic throughout, deterministic. Errors: WICK_EINVAL (null or
+ * misaligned pointers, bad sizes), WICK_ENOMEM, WICK_EHIP. Asynchronous on
+ * stream. */
+wick_status wick_point_correlator(wick_point_t plan, const void *S_u, const void *S_d, wick_dtype dtype,
+                                  const int32_t dims[4], int32_t n_cfg, wick_stream_t stream, double *C);
+void wick_point_destroy(wick_point_t plan);
+
 /* Release the device workspace (blocking). */
 wick_status wick_shutdown(void);
 

@@ -13,6 +13,9 @@ Routes to C(t) for one time slice (all FP64, compensated accumulation):
   every flavor-preserving bijection with its sign (Eq. 2.6 / App. D).
 * ``sum_dp``: blocks, the source antisymmetrised first (method A, Sec. 3.3),
   then a dynamic programme over used source positions.
+* ``point_correlator``: a point sink (every quark of the sink at one site,
+  summed over sites, Eq. 2.9): the one-site lattice's blocks and the DP route
+  per site. No determinants are involved.
 * ``term_list`` / ``merged_terms``: the block-form terms themselves (one per
   canonical slot assignment, then merged by monomial), the objects that the
   important-term study of Sec. 5 and App. D ranks; ``important_terms`` is that
@@ -68,6 +71,8 @@ def lib():
         L.oracle_source_group_count.restype = ctypes.c_long
         L.oracle_threads.restype = ctypes.c_int32
         L.oracle_term_list.argtypes = [i32] + kinds + pats + [P, P]
+        L.oracle_source_groups.argtypes = [i32] + kinds + [i32, P, P, i32, P, P]
+        L.oracle_source_groups.restype = ctypes.c_long
         L.oracle_term_list.restype = ctypes.c_long
         _lib = L
     return _lib
@@ -272,3 +277,87 @@ def important_terms(keys, coef, B_eq24, keep):
     kept[order[:M]] = True
     dropped = mag[:, ~kept].sum(axis=1)
     return kept, score, dropped
+
+
+# ------------------------------------------------------------- point sinks
+def source_groups(op):
+    """Antisymmetrised source groups: (vals [G, 3A] canonical index lists, u's
+    ascending then d's ascending; W' [G] complex128, unscaled)."""
+    pk = _Packed(op)
+    nu = sum(1 for f in operators.flavor_listing(op, op.src[0][0]) if f == 0)
+    args = [op.A, *pk.kinds_args(), pk.n_src, _p(pk.src_k), _p(pk.src_c), nu]
+    n = int(lib().oracle_source_groups(*args, None, None))
+    vals = np.zeros((max(n, 1), 3 * op.A), dtype=np.int32)
+    w = np.zeros((max(n, 1), 2))
+    lib().oracle_source_groups(*args, _p(vals), _p(w))
+    return vals[:n], w[:n, 0] + 1j * w[:n, 1]
+
+
+def point_correlator(op, Su, Sd, t_slices=None):
+    """Scaled point-sink C(t) for propagators [T, Z, Y, X, 12, 12]: the sink's
+    quarks all at one site x, summed over x (Eq. 2.9). Per site, the blocks of
+    that one-site lattice and the DP route of the block form; no determinants."""
+    T = Su.shape[0]
+    ts = range(T) if t_slices is None else t_slices
+    out = np.zeros(len(ts), dtype=np.complex128)
+    for n, t in enumerate(ts):
+        su = _site_major(Su[t])
+        sd = _site_major(Sd[t])
+        c = 0j
+        for x in range(su.shape[0]):
+            c += sum_dp(op, blocks_raw(op, su[x:x + 1], sd[x:x + 1]))
+        out[n] = op.scale * c
+    return out
+
+
+def point_magnitude(op, Su, Sd, keys, coef, t_slices=None):
+    """Sum over sites of sum_n |merged term n| on the one-site blocks (the
+    error scale of a point-sink C(t)); keys, coef from merged_terms(op)."""
+    T = Su.shape[0]
+    ts = range(T) if t_slices is None else t_slices
+    out = np.zeros(len(ts))
+    for n, t in enumerate(ts):
+        su = _site_major(Su[t])
+        sd = _site_major(Sd[t])
+        for x in range(su.shape[0]):
+            B = np.stack([block_eq24(k, su[x:x + 1], sd[x:x + 1]) for k in op.kinds])[None]
+            out[n] += np.abs(term_values(keys, coef, B)).sum()
+    return out
+
+
+def point_det_magnitude(op, Su, Sd, t_slices=None):
+    """Per time slice, sum over sites of sum_{g,h} |W_g W'_h det S_u[U_g; U'_h]
+    det S_d[D_g; D'_h]|: the absolute terms of the determinant form of Eq. 2.9
+    (numpy determinants), the error scale of a point-sink C(t). Unscaled by
+    op.scale's sign, scaled by its magnitude."""
+    from .operators import Operator
+    sink = Operator(op.A, op.kinds, op.snk, op.snk, op.scale, op.name)
+    vs, ws = source_groups(sink)
+    vh, wh = source_groups(op)
+    nu = sum(1 for f in operators.flavor_listing(op, op.snk[0][0]) if f == 0)
+
+    def split(v):
+        U, iu = np.unique(v[:, :nu], axis=0, return_inverse=True)
+        D, idd = np.unique(v[:, nu:], axis=0, return_inverse=True)
+        return U, iu.reshape(-1), D, idd.reshape(-1)
+
+    Us, ius, Ds, ids = split(vs)
+    Uh, iuh, Dh, idh = split(vh)
+
+    def dets(M, R, K):
+        sub = M[R[:, None, :, None], K[None, :, None, :]]
+        return np.abs(np.linalg.det(sub)) if R.shape[1] else np.ones((len(R), len(K)))
+
+    T = Su.shape[0]
+    ts = range(T) if t_slices is None else t_slices
+    out = np.zeros(len(ts))
+    aws, awh = np.abs(ws), np.abs(wh)
+    for n, t in enumerate(ts):
+        su = _site_major(Su[t])
+        sd = _site_major(Sd[t])
+        for x in range(su.shape[0]):
+            du = dets(su[x], Us, Uh)
+            dd = dets(sd[x], Ds, Dh)
+            A = du[ius][:, iuh] * dd[ids][:, idh]
+            out[n] += aws @ A @ awh
+    return abs(op.scale) * out

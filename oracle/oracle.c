@@ -677,6 +677,28 @@ long oracle_term_list(int32_t A, int32_t K, const int32_t *flav, const int32_t *
     return cnt;
 }
 
+/* The antisymmetrised source groups themselves (method A of Sec. 3.3):
+ * canonical index lists (n values each: u's ascending, then d's ascending)
+ * and weights W'(U, D). With vals == NULL only the count is returned. */
+long oracle_source_groups(int32_t A, int32_t K, const int32_t *flav, const int32_t *nw, const int32_t *woff,
+                          const int32_t *wj, const double *wre, const double *wim, int32_t n_src,
+                          const int32_t *src_kind, const double *src_c, int32_t n_u, int32_t *vals, double *w)
+{
+    kinds_t ks = {K, flav, nw, woff, wj, wre, wim};
+    grp_t *gr;
+    long ng = source_groups(&ks, A, n_src, src_kind, src_c, n_u, &gr);
+    const int n = 3 * A;
+    if (vals)
+        for (long g = 0; g < ng; ++g) {
+            uint64_t key = gr[g].key;
+            for (int p = n - 1; p >= 0; --p) { vals[g * n + p] = (int32_t)(key & 15); key >>= 4; }
+            w[2 * g] = creal(gr[g].w);
+            w[2 * g + 1] = cimag(gr[g].w);
+        }
+    free(gr);
+    return ng;
+}
+
 /* Number of OpenMP threads the oracle's parallel loops use. */
 int32_t oracle_threads(void)
 {

@@ -38,13 +38,21 @@ wick_status hip_fail(hipError_t e, const char *what)
     return fail(WICK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+}  // namespace
+
 // ------------------------------------------------------------- workspaces
+namespace {
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
 };
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+wick_status ws_hip_fail(hipError_t e, const char *what)
+{
+    return fail(WICK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+}  // namespace
 
 // A device buffer of at least `bytes` private to (device, stream). Growing it
 // waits for the stream, so earlier work that used the old buffer is done.
@@ -52,13 +60,13 @@ wick_status workspace(hipStream_t s, size_t bytes, void **out)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (e != hipSuccess) return ws_hip_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace &w = g_ws[{dev, s}];
     if (w.bytes < bytes) {
         if (w.ptr) {
             e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            if (e != hipSuccess) return ws_hip_fail(e, "hipStreamSynchronize");
             (void)hipFree(w.ptr);
             w.ptr = nullptr;
             w.bytes = 0;
@@ -71,6 +79,8 @@ wick_status workspace(hipStream_t s, size_t bytes, void **out)
     *out = w.ptr;
     return WICK_OK;
 }
+
+namespace {
 
 void release_workspace(hipStream_t s)
 {

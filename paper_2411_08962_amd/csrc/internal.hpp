@@ -82,6 +82,27 @@ struct wick_plan_s {
     ~wick_plan_s();
 };
 
+// A point-sink plan (Eq. 2.9 and App. A): sink and source coefficient tensors
+// antisymmetrised per flavor into groups (U, D) of sorted index lists, the
+// distinct sink row sets, and the source column sets as ranks among the
+// k-subsets of the 12 spin-colour indices.
+struct wick_point_s {
+    int n_u = 0, n_d = 0;               // quarks of each flavor
+    double scale = 1.0;
+    std::vector<std::array<int8_t, 8>> rows_u, rows_d;  // distinct sink row sets
+    // sink groups, sorted by (u row set, d row set)
+    std::vector<int32_t> g_u, g_d;      // indices into rows_u, rows_d
+    std::vector<double> g_w;            // [2 G] exact integer weights (re, im)
+    std::vector<int32_t> u_beg;         // [n rows_u + 1] sink groups of each u row set
+    // source groups
+    std::vector<uint16_t> h_ru, h_rd;   // colex ranks of the column sets U', D'
+    std::vector<double> h_w;            // [2 H]
+    int64_t n_cols_u = 0, n_cols_d = 0; // distinct source column sets
+    std::mutex dev_mu;
+    std::vector<void *> dev;            // device tables, one per device (point.hip)
+    ~wick_point_s();
+};
+
 namespace wick {
 
 void set_error(const std::string &msg);
@@ -100,6 +121,11 @@ wick_status truncate_plan(const wick_plan_s *p, const double *B_cal, int32_t n_s
 
 // built-in operators (nuclei.cpp)
 wick_status std_plan(const char *name, int32_t J, wick_plan_t *out);
+wick_status std_point_plan(const char *name, int32_t J, wick_point_t *out);
+
+// point-sink planner (point.cpp) and device tables (point.hip)
+wick_status build_point_plan(const wick_nucleus_desc *d, wick_point_t *out);
+void release_point_tables(wick_point_s *p);
 
 // device-table release (api.cpp)
 void release_device_tables(wick_plan_s *p);

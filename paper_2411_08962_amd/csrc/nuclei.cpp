@@ -131,7 +131,9 @@ struct OpBuilder {
         re.push_back(c);
         im.push_back(0);
     }
-    wick_status plan(wick_plan_t *out)
+    // The operator as a wick_nucleus_desc (valid during the call of f).
+    template <class F>
+    wick_status with_desc(F &&f)
     {
         std::vector<wick_kind> wk(kinds.size());
         for (size_t i = 0; i < kinds.size(); ++i) {
@@ -150,7 +152,7 @@ struct OpBuilder {
         d.snk_re = d.src_re = re.data();
         d.snk_im = d.src_im = im.data();
         d.scale = scale;
-        return build_plan(&d, out);
+        return f(&d);
     }
 };
 
@@ -158,11 +160,12 @@ int cg5_int(int a, int b) { return basis().cg5[a][b].real(); }
 
 }  // namespace
 
-wick_status std_plan(const char *name, int32_t J, wick_plan_t *out)
+namespace {
+
+wick_status std_operator(const char *name, int32_t J, OpBuilder &ob)
 {
-    if (!name || !out) return fail(WICK_EINVAL, "wick_plan_std: null argument");
+    if (!name) return fail(WICK_EINVAL, "wick_plan_std: null argument");
     std::string n(name);
-    OpBuilder ob;
     if (n == "1H") {
         if (J < 0 || J > 3) return fail(WICK_EINVAL, "wick_plan_std: J must be 0..3");
         ob.A = 1;
@@ -201,7 +204,27 @@ wick_status std_plan(const char *name, int32_t J, wick_plan_t *out)
     } else {
         return fail(WICK_EINVAL, "wick_plan_std: unknown nucleus '" + n + "' (1H, 2H, 3He, 3H, 4He)");
     }
-    return ob.plan(out);
+    return WICK_OK;
+}
+
+}  // namespace
+
+wick_status std_plan(const char *name, int32_t J, wick_plan_t *out)
+{
+    if (!out) return fail(WICK_EINVAL, "wick_plan_std: null argument");
+    OpBuilder ob;
+    wick_status st = std_operator(name, J, ob);
+    if (st != WICK_OK) return st;
+    return ob.with_desc([&](const wick_nucleus_desc *d) { return build_plan(d, out); });
+}
+
+wick_status std_point_plan(const char *name, int32_t J, wick_point_t *out)
+{
+    if (!out) return fail(WICK_EINVAL, "wick_point_plan_std: null argument");
+    OpBuilder ob;
+    wick_status st = std_operator(name, J, ob);
+    if (st != WICK_OK) return st;
+    return ob.with_desc([&](const wick_nucleus_desc *d) { return build_point_plan(d, out); });
 }
 
 }  // namespace wick

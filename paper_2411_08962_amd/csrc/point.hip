@@ -1,0 +1,442 @@
+// Point-sink correlators by determinants (Sec. 3.1 Eq. 2.9, App. A Eq. A1):
+// device tables, kernels and the wick_point_correlator entry point.
+//
+// Per site-slice (configuration, t, x) the minimal set is every
+// det S_f[R; K] for a sink row set R and a source column set K of flavor f.
+// Instead of one factorisation per determinant, all minors of the rows R are
+// built by Laplace expansion along the last row, level by level over the
+// column subsets: the k x k minors of rows R[0..k) are
+//   M_k(c) = sum_j (-1)^(k-1+j) S[R[k-1]][c_j] M_{k-1}(c \ c_j)
+// for every k-subset c of the 12 columns (colex-ranked). Level n holds
+// det S[R; K] for every column set K at once; building all levels costs
+// sum_k binom(12,k) k complex multiply-adds per row set (6744 for n = 5),
+// a few per determinant, and is division-free.
+//
+// Kernels (one site-slice per "slot"):
+//   pt_minors_kernel: the d minors of every sink row set, kept for the
+//     source column sets only, to a workspace [slot][row set][column set].
+//   pt_pairs_kernel: the u minors of a chunk of sink row sets in LDS, then
+//     for every sink group g of those row sets the sum over source groups h
+//     of W'_h det_u[U_g; U'_h] det_d[D_g; D'_h], times W_g (the Theta-weighted
+//     double sum of Eq. A1), into one partial per (slot, chunk).
+//   pt_reduce_kernel: C[cfg][t] = scale * the sum of the partials of its slots
+//     in a fixed order (deterministic).
+// The host walks the site-slices in chunks that bound the d workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace wick {
+
+wick_status workspace(hipStream_t s, size_t bytes, void **out);
+
+namespace {
+
+constexpr int kPtThreads = 256;
+constexpr int kPtMaxMinors = 924;   // binom(12, 6)
+constexpr int kPtSubsets = 2509;    // sum_{k=1..6} binom(12, k)
+constexpr int kPtRowsPerWG = 8;     // sink row sets per workgroup
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Level tables: for level k (1..6) and colex rank r < binom(12, k), entry
+// e = off[k] + r holds the subset's elements and, for each j, the rank of the
+// subset without element j (a (k-1)-subset).
+struct PtSubsets {
+    int32_t off[8];
+    int32_t cnt[8];
+    uint8_t elem[kPtSubsets][6];
+    uint16_t sub[kPtSubsets][6];
+};
+
+struct PtDev {
+    int device = -1;
+    PtSubsets *sub = nullptr;
+    int8_t *rows_u = nullptr, *rows_d = nullptr;   // [n][8]
+    int32_t *u_beg = nullptr, *g_d = nullptr;
+    double2 *g_w = nullptr;
+    uint16_t *h_ru = nullptr, *h_cd = nullptr;     // u column rank, d compact column index
+    double2 *h_w = nullptr;
+    uint16_t *d_cols = nullptr;                    // compact d column index -> rank
+    int n_cd = 0;
+};
+
+struct PtArgs {
+    const PtSubsets *sub;
+    const int8_t *rows_u, *rows_d;
+    const int32_t *u_beg, *g_d;
+    const double2 *g_w;
+    const uint16_t *h_ru, *h_cd, *d_cols;
+    const double2 *h_w;
+    int n_u, n_d, n_rows_u, n_rows_d, n_h, n_cd;
+    int n_uchunks, n_dchunks;
+    int64_t slot0;       // first site-slice of this launch
+    int n_slots;         // site-slices in this launch
+    double2 *dd;         // [n_slots][n_rows_d][n_cd]
+    double2 *partial;    // [total slots][n_uchunks]
+};
+
+__device__ __forceinline__ int xcd_id(int nb)
+{
+    const int b = blockIdx.x;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+template <typename TIn>
+__device__ __forceinline__ void stage_site(const TIn *__restrict__ S, int64_t slot, double2 *sS)
+{
+    const TIn *p = S + slot * 144;
+    for (int e = threadIdx.x; e < 144; e += kPtThreads) sS[e] = make_double2((double)p[e].x, (double)p[e].y);
+}
+
+// All minors of rows R[0..n) of the staged 12x12 matrix; returns the LDS
+// buffer that holds level n (binom(12, n) entries by colex rank).
+__device__ double2 *minors(const PtSubsets *__restrict__ T, const double2 *sS, const int8_t *R, int n,
+                           double2 *buf0, double2 *buf1)
+{
+    if (threadIdx.x == 0) buf0[0] = make_double2(1.0, 0.0);
+    __syncthreads();
+    double2 *prev = buf0, *cur = buf1;
+    for (int k = 1; k <= n; ++k) {
+        const int row = R[k - 1];
+        const int off = T->off[k], cnt = T->cnt[k];
+        for (int r = threadIdx.x; r < cnt; r += kPtThreads) {
+            const uint8_t *el = T->elem[off + r];
+            const uint16_t *sb = T->sub[off + r];
+            double2 s = make_double2(0.0, 0.0);
+            for (int j = 0; j < k; ++j) {
+                const double2 t = cmul(sS[row * 12 + el[j]], prev[sb[j]]);
+                if ((k - 1 + j) & 1) { s.x -= t.x; s.y -= t.y; }
+                else { s.x += t.x; s.y += t.y; }
+            }
+            cur[r] = s;
+        }
+        __syncthreads();
+        double2 *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    return prev;
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(kPtThreads) void pt_minors_kernel(const TIn *__restrict__ Sd, PtArgs a)
+{
+    __shared__ double2 sS[144];
+    __shared__ double2 buf[2][kPtMaxMinors];
+    const int total = a.n_slots * a.n_dchunks;
+    const int id = xcd_id(gridDim.x);
+    if (id >= total) return;
+    const int slot = id / a.n_dchunks, chunk = id % a.n_dchunks;
+    stage_site(Sd, a.slot0 + slot, sS);
+    __syncthreads();
+    const int r0 = chunk * kPtRowsPerWG, r1 = min(a.n_rows_d, r0 + kPtRowsPerWG);
+    for (int r = r0; r < r1; ++r) {
+        const double2 *L = minors(a.sub, sS, a.rows_d + 8 * r, a.n_d, buf[0], buf[1]);
+        double2 *out = a.dd + ((int64_t)slot * a.n_rows_d + r) * a.n_cd;
+        for (int c = threadIdx.x; c < a.n_cd; c += kPtThreads) out[c] = L[a.d_cols[c]];
+        __syncthreads();
+    }
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(kPtThreads) void pt_pairs_kernel(const TIn *__restrict__ Su, PtArgs a)
+{
+    __shared__ double2 sS[144];
+    __shared__ double2 buf[2][kPtMaxMinors];
+    __shared__ double2 red[kPtThreads / 64];
+    const int total = a.n_slots * a.n_uchunks;
+    const int id = xcd_id(gridDim.x);
+    if (id >= total) return;
+    const int slot = id / a.n_uchunks, chunk = id % a.n_uchunks;
+    stage_site(Su, a.slot0 + slot, sS);
+    __syncthreads();
+    double2 tot = make_double2(0.0, 0.0);
+    const int r0 = chunk * kPtRowsPerWG, r1 = min(a.n_rows_u, r0 + kPtRowsPerWG);
+    const double2 *ddslot = a.dd + (int64_t)slot * a.n_rows_d * a.n_cd;
+    for (int r = r0; r < r1; ++r) {
+        const double2 *L = minors(a.sub, sS, a.rows_u + 8 * r, a.n_u, buf[0], buf[1]);
+        for (int g = a.u_beg[r]; g < a.u_beg[r + 1]; ++g) {
+            const double2 *drow = ddslot + (int64_t)a.g_d[g] * a.n_cd;
+            double2 s = make_double2(0.0, 0.0);
+            for (int h = threadIdx.x; h < a.n_h; h += kPtThreads) {
+                const double2 t = cmul(cmul(a.h_w[h], L[a.h_ru[h]]), drow[a.h_cd[h]]);
+                s.x += t.x;
+                s.y += t.y;
+            }
+            const double2 t = cmul(a.g_w[g], s);
+            tot.x += t.x;
+            tot.y += t.y;
+        }
+        __syncthreads();
+    }
+    // workgroup sum: wave shuffle tree, then the waves in order
+    for (int o = 32; o > 0; o >>= 1) {
+        tot.x += __shfl_down(tot.x, o, 64);
+        tot.y += __shfl_down(tot.y, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double2 s = red[0];
+        for (int w = 1; w < kPtThreads / 64; ++w) { s.x += red[w].x; s.y += red[w].y; }
+        a.partial[(a.slot0 + slot) * a.n_uchunks + chunk] = s;
+    }
+}
+
+__global__ __launch_bounds__(kPtThreads) void pt_reduce_kernel(const double2 *__restrict__ partial, int64_t per_ct,
+                                                              double scale, double2 *__restrict__ C)
+{
+    __shared__ double2 red[kPtThreads];
+    const int64_t ct = blockIdx.x;
+    const double2 *p = partial + ct * per_ct;
+    double2 s = make_double2(0.0, 0.0);
+    for (int64_t i = threadIdx.x; i < per_ct; i += kPtThreads) { s.x += p[i].x; s.y += p[i].y; }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kPtThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) { red[threadIdx.x].x += red[threadIdx.x + o].x; red[threadIdx.x].y += red[threadIdx.x + o].y; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) C[ct] = make_double2(scale * red[0].x, scale * red[0].y);
+}
+
+// ------------------------------------------------------------ host side
+wick_status pt_hip_fail(hipError_t e, const char *what)
+{
+    return fail(WICK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int64_t binom12(int k)
+{
+    int64_t r = 1;
+    for (int i = 0; i < k; ++i) r = r * (12 - i) / (i + 1);
+    return r;
+}
+
+void build_subsets(PtSubsets &T)
+{
+    std::memset(&T, 0, sizeof(T));
+    int e = 0;
+    for (int k = 0; k <= 6; ++k) {
+        T.off[k] = k == 0 ? 0 : e;
+        T.cnt[k] = (int)binom12(k);
+        if (k == 0) continue;
+        // colex order of k-subsets = increasing bitmask
+        std::vector<int> rank_of(4096, -1);
+        int r = 0;
+        for (int m = 0; m < 4096; ++m)
+            if (__builtin_popcount(m) == k) rank_of[m] = r++;
+        std::vector<int> rank_prev(4096, -1);
+        r = 0;
+        for (int m = 0; m < 4096; ++m)
+            if (__builtin_popcount(m) == k - 1) rank_prev[m] = r++;
+        for (int m = 0; m < 4096; ++m) {
+            if (__builtin_popcount(m) != k) continue;
+            int j = 0;
+            for (int c = 0; c < 12; ++c)
+                if (m >> c & 1) {
+                    T.elem[e + rank_of[m]][j] = (uint8_t)c;
+                    T.sub[e + rank_of[m]][j] = (uint16_t)rank_prev[m & ~(1 << c)];
+                    ++j;
+                }
+        }
+        e += T.cnt[k];
+    }
+}
+
+template <class T>
+wick_status upload(const std::vector<T> &v, T **out)
+{
+    const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
+    hipError_t e = hipMalloc((void **)out, bytes);
+    if (e != hipSuccess) return fail(WICK_ENOMEM, std::string("wick_point: hipMalloc: ") + hipGetErrorString(e));
+    if (!v.empty()) {
+        e = hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return pt_hip_fail(e, "wick_point: hipMemcpy");
+    }
+    return WICK_OK;
+}
+
+void free_dev(PtDev *d)
+{
+    (void)hipFree(d->sub);
+    (void)hipFree(d->rows_u);
+    (void)hipFree(d->rows_d);
+    (void)hipFree(d->u_beg);
+    (void)hipFree(d->g_d);
+    (void)hipFree(d->g_w);
+    (void)hipFree(d->h_ru);
+    (void)hipFree(d->h_cd);
+    (void)hipFree(d->h_w);
+    (void)hipFree(d->d_cols);
+    delete d;
+}
+
+wick_status device_tables(wick_point_s *p, PtDev **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return pt_hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(p->dev_mu);
+    for (void *v : p->dev)
+        if (((PtDev *)v)->device == dev) { *out = (PtDev *)v; return WICK_OK; }
+    auto d = new PtDev();
+    d->device = dev;
+    PtSubsets T;
+    build_subsets(T);
+    std::vector<PtSubsets> tv(1, T);
+    std::vector<int8_t> ru, rd;
+    for (auto &r : p->rows_u) ru.insert(ru.end(), r.begin(), r.end());
+    for (auto &r : p->rows_d) rd.insert(rd.end(), r.begin(), r.end());
+    std::vector<double2> gw(p->g_u.size()), hw(p->h_ru.size());
+    for (size_t i = 0; i < gw.size(); ++i) gw[i] = make_double2(p->g_w[2 * i], p->g_w[2 * i + 1]);
+    for (size_t i = 0; i < hw.size(); ++i) hw[i] = make_double2(p->h_w[2 * i], p->h_w[2 * i + 1]);
+    // compact d columns: the source column sets that occur
+    std::map<int, int> cols;
+    for (uint16_t r : p->h_rd) cols.emplace(r, 0);
+    std::vector<uint16_t> dcols, hcd(p->h_rd.size());
+    for (auto &c : cols) { c.second = (int)dcols.size(); dcols.push_back((uint16_t)c.first); }
+    for (size_t i = 0; i < hcd.size(); ++i) hcd[i] = (uint16_t)cols[p->h_rd[i]];
+    d->n_cd = (int)dcols.size();
+    wick_status st;
+    if ((st = upload(tv, &d->sub)) != WICK_OK || (st = upload(ru, &d->rows_u)) != WICK_OK ||
+        (st = upload(rd, &d->rows_d)) != WICK_OK || (st = upload(p->u_beg, &d->u_beg)) != WICK_OK ||
+        (st = upload(p->g_d, &d->g_d)) != WICK_OK || (st = upload(gw, &d->g_w)) != WICK_OK ||
+        (st = upload(p->h_ru, &d->h_ru)) != WICK_OK || (st = upload(hcd, &d->h_cd)) != WICK_OK ||
+        (st = upload(hw, &d->h_w)) != WICK_OK || (st = upload(dcols, &d->d_cols)) != WICK_OK) {
+        free_dev(d);
+        return st;
+    }
+    p->dev.push_back(d);
+    *out = d;
+    return WICK_OK;
+}
+
+int64_t check_point_dims(const int32_t dims[4], int32_t n_cfg)
+{
+    if (!dims || n_cfg < 1) return -1;
+    for (int i = 0; i < 4; ++i)
+        if (dims[i] < 1) return -1;
+    const int64_t V = (int64_t)dims[0] * dims[1] * dims[2];
+    if (V > (1LL << 30) || (int64_t)n_cfg * dims[3] > (1LL << 24)) return -2;
+    return V;
+}
+
+template <typename TIn>
+wick_status launch_point(wick_point_s *p, PtDev *d, const TIn *Su, const TIn *Sd, int64_t V, int64_t n_ct,
+                         hipStream_t s, double2 *C)
+{
+    const int64_t slots = V * n_ct;
+    if (p->g_u.empty() || p->h_ru.empty()) {
+        // no sink or no source groups: C is zero (a fill kernel, also inside graph capture)
+        hipError_t e = launch_zero((double *)C, 2 * n_ct, s);
+        return e == hipSuccess ? WICK_OK : pt_hip_fail(e, "zero_kernel");
+    }
+    PtArgs a{};
+    a.sub = d->sub;
+    a.rows_u = d->rows_u;
+    a.rows_d = d->rows_d;
+    a.u_beg = d->u_beg;
+    a.g_d = d->g_d;
+    a.g_w = d->g_w;
+    a.h_ru = d->h_ru;
+    a.h_cd = d->h_cd;
+    a.d_cols = d->d_cols;
+    a.h_w = d->h_w;
+    a.n_u = p->n_u;
+    a.n_d = p->n_d;
+    a.n_rows_u = (int)p->rows_u.size();
+    a.n_rows_d = (int)p->rows_d.size();
+    a.n_h = (int)p->h_ru.size();
+    a.n_cd = d->n_cd;
+    a.n_uchunks = (a.n_rows_u + kPtRowsPerWG - 1) / kPtRowsPerWG;
+    a.n_dchunks = (a.n_rows_d + kPtRowsPerWG - 1) / kPtRowsPerWG;
+    const size_t per_slot_dd = (size_t)a.n_rows_d * a.n_cd * sizeof(double2);
+    const size_t partial_bytes = (size_t)slots * a.n_uchunks * sizeof(double2);
+    int64_t chunk = std::max<int64_t>(8, (int64_t)((512ull << 20) / std::max<size_t>(per_slot_dd, 1)) / 8 * 8);
+    chunk = std::min<int64_t>(chunk, slots);
+    const int64_t max_wg = (1LL << 31) - 64;
+    chunk = std::min<int64_t>(chunk, max_wg / std::max(a.n_uchunks, a.n_dchunks));
+    void *ws = nullptr;
+    const size_t part_off = ((size_t)chunk * per_slot_dd + 255) / 256 * 256;
+    wick_status st = workspace(s, part_off + partial_bytes, &ws);
+    if (st != WICK_OK) return st;
+    a.dd = (double2 *)ws;
+    a.partial = (double2 *)((char *)ws + part_off);
+    for (int64_t s0 = 0; s0 < slots; s0 += chunk) {
+        a.slot0 = s0;
+        a.n_slots = (int)std::min<int64_t>(chunk, slots - s0);
+        const int64_t nd = (int64_t)a.n_slots * a.n_dchunks, nu = (int64_t)a.n_slots * a.n_uchunks;
+        Probe pa("point_minors", s);
+        pt_minors_kernel<TIn><<<dim3((unsigned)((nd + 7) / 8 * 8)), dim3(kPtThreads), 0, s>>>(Sd, a);
+        pa.stop();
+        Probe pb("point_pairs", s);
+        pt_pairs_kernel<TIn><<<dim3((unsigned)((nu + 7) / 8 * 8)), dim3(kPtThreads), 0, s>>>(Su, a);
+        pb.stop();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return pt_hip_fail(e, "point kernels");
+    }
+    Probe pc("point_reduce", s);
+    pt_reduce_kernel<<<dim3((unsigned)n_ct), dim3(kPtThreads), 0, s>>>(a.partial, V * a.n_uchunks, p->scale, C);
+    pc.stop();
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? WICK_OK : pt_hip_fail(e, "pt_reduce_kernel");
+}
+
+}  // namespace
+
+void release_point_tables(wick_point_s *p)
+{
+    std::lock_guard<std::mutex> lk(p->dev_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (void *v : p->dev) {
+        PtDev *d = (PtDev *)v;
+        (void)hipSetDevice(d->device);
+        free_dev(d);
+    }
+    p->dev.clear();
+    (void)hipSetDevice(cur);
+}
+
+}  // namespace wick
+
+using namespace wick;
+
+extern "C" wick_status wick_point_correlator(wick_point_t p, const void *S_u, const void *S_d, wick_dtype dtype,
+                                             const int32_t dims[4], int32_t n_cfg, wick_stream_t stream, double *C)
+{
+    try {
+        if (!p || !S_u || !S_d || !C) return fail(WICK_EINVAL, "wick_point_correlator: null pointer");
+        if (((uintptr_t)S_u | (uintptr_t)S_d | (uintptr_t)C) & 15)
+            return fail(WICK_EINVAL, "wick_point_correlator: propagators and C must be 16-byte aligned");
+        if (dtype != WICK_C128 && dtype != WICK_C64) return fail(WICK_EINVAL, "wick_point_correlator: bad dtype");
+        const int64_t V = check_point_dims(dims, n_cfg);
+        if (V == -1) return fail(WICK_EINVAL, "wick_point_correlator: bad dims or n_cfg");
+        if (V < 0) return fail(WICK_ETOOBIG, "wick_point_correlator: lattice too large");
+        const int64_t n_ct = (int64_t)n_cfg * dims[3];
+        if ((int64_t)(p->rows_u.size() + kPtRowsPerWG) / kPtRowsPerWG * V * n_ct > (1LL << 40))
+            return fail(WICK_ETOOBIG, "wick_point_correlator: too many partial sums");
+        PtDev *d = nullptr;
+        wick_status st = device_tables(p, &d);
+        if (st != WICK_OK) return st;
+        hipStream_t s = (hipStream_t)stream;
+        if (dtype == WICK_C128)
+            return launch_point(p, d, (const double2 *)S_u, (const double2 *)S_d, V, n_ct, s, (double2 *)C);
+        return launch_point(p, d, (const float2 *)S_u, (const float2 *)S_d, V, n_ct, s, (double2 *)C);
+    } catch (const std::bad_alloc &) {
+        return fail(WICK_ENOMEM, "wick_point_correlator: out of host memory");
+    } catch (...) {
+        return fail(WICK_EINVAL, "wick_point_correlator: internal error");
+    }
+}

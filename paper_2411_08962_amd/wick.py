@@ -50,7 +50,8 @@ class _Item(ctypes.Structure):
 EXPORTS = ["wick_plan", "wick_plan_std", "wick_plan_info", "wick_plan_stats", "wick_plan_table",
            "wick_plan_kind", "wick_plan_save", "wick_plan_load", "wick_plan_truncate", "wick_plan_destroy", "wick_blocks",
            "wick_contract", "wick_correlator", "wick_autotune", "wick_shutdown", "wick_last_error",
-           "wick_version", "wick_profile", "wick_profile_read"]
+           "wick_version", "wick_profile", "wick_profile_read", "wick_point_plan", "wick_point_plan_std",
+           "wick_point_info", "wick_point_correlator", "wick_point_destroy"]
 
 _lib = None
 
@@ -84,12 +85,19 @@ def lib():
     L.wick_shutdown.argtypes = []
     L.wick_profile.argtypes = [i32]
     L.wick_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
+    L.wick_point_plan.argtypes = [ctypes.POINTER(_Desc), pp]
+    L.wick_point_plan_std.argtypes = [ctypes.c_char_p, i32, pp]
+    L.wick_point_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)] + [ctypes.POINTER(i64)] * 6
+    L.wick_point_correlator.argtypes = [P, P, P, st, P, i32, P, P]
+    L.wick_point_destroy.argtypes = [P]
+    L.wick_point_destroy.restype = None
     L.wick_last_error.restype = ctypes.c_char_p
     L.wick_version.restype = ctypes.c_char_p
     for name in ("wick_plan", "wick_plan_std", "wick_plan_info", "wick_plan_stats", "wick_plan_table",
                  "wick_plan_kind", "wick_plan_save", "wick_plan_load", "wick_plan_truncate", "wick_blocks",
                  "wick_contract",
-                 "wick_correlator", "wick_autotune", "wick_shutdown", "wick_profile", "wick_profile_read"):
+                 "wick_correlator", "wick_autotune", "wick_shutdown", "wick_profile", "wick_profile_read",
+                 "wick_point_plan", "wick_point_plan_std", "wick_point_info", "wick_point_correlator"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -200,12 +208,8 @@ def plan_std(nucleus, J=0):
     return Plan(h.value)
 
 
-def plan(A, kinds, snk, src, scale=1.0, hash_seed=0, hash_trials=0, hash_sites=0):
-    """Plan a general operator.
-
-    kinds: list of (flavors (3,), weights [(j1, j2, j3, w_re, w_im), ...]);
-    snk, src: list of (tuple of A kind indices, (c_re, c_im)).
-    """
+def _desc(A, kinds, snk, src, scale=1.0, hash_seed=0, hash_trials=0, hash_sites=0):
+    """The operator as a wick_nucleus_desc; returns (desc, arrays to keep alive)."""
     keep = []
     ks = (_Kind * len(kinds))()
     for i, (fl, w) in enumerate(kinds):
@@ -218,6 +222,7 @@ def plan(A, kinds, snk, src, scale=1.0, hash_seed=0, hash_trials=0, hash_sites=0
         ks[i].j = j.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
         ks[i].w_re = re.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
         ks[i].w_im = im.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    keep.append(ks)
 
     def pats(ps):
         k = np.array([x for p in ps for x in p[0]], dtype=np.int32)
@@ -232,9 +237,58 @@ def plan(A, kinds, snk, src, scale=1.0, hash_seed=0, hash_trials=0, hash_sites=0
     d.n_snk, d.snk_kind, d.snk_re, d.snk_im = pats(snk)
     d.n_src, d.src_kind, d.src_re, d.src_im = pats(src)
     d.scale, d.hash_seed, d.hash_trials, d.hash_sites = float(scale), int(hash_seed), int(hash_trials), int(hash_sites)
+    return d, keep
+
+
+def plan(A, kinds, snk, src, scale=1.0, hash_seed=0, hash_trials=0, hash_sites=0):
+    """Plan a general operator.
+
+    kinds: list of (flavors (3,), weights [(j1, j2, j3, w_re, w_im), ...]);
+    snk, src: list of (tuple of A kind indices, (c_re, c_im)).
+    """
+    d, keep = _desc(A, kinds, snk, src, scale, hash_seed, hash_trials, hash_sites)
     h = ctypes.c_void_p()
     _check(lib().wick_plan(ctypes.byref(d), ctypes.byref(h)))
     return Plan(h.value)
+
+
+class PointPlan:
+    """A point-sink determinant plan (owned by the library)."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.wick_point_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def info(self):
+        nu, nd = ctypes.c_int32(), ctypes.c_int32()
+        v = [ctypes.c_int64() for _ in range(6)]
+        _check(lib().wick_point_info(self._h, ctypes.byref(nu), ctypes.byref(nd), *[ctypes.byref(x) for x in v]))
+        keys = ("n_sink_groups", "n_src_groups", "n_rows_u", "n_cols_u", "n_rows_d", "n_cols_d")
+        out = {"n_u": nu.value, "n_d": nd.value}
+        out.update({k: x.value for k, x in zip(keys, v)})
+        return out
+
+
+def point_plan(A, kinds, snk, src, scale=1.0):
+    """Point-sink plan of a general operator (same arguments as plan())."""
+    d, keep = _desc(A, kinds, snk, src, scale)
+    h = ctypes.c_void_p()
+    _check(lib().wick_point_plan(ctypes.byref(d), ctypes.byref(h)))
+    return PointPlan(h.value)
+
+
+def point_plan_std(nucleus, J=0):
+    h = ctypes.c_void_p()
+    _check(lib().wick_point_plan_std(nucleus.encode(), int(J), ctypes.byref(h)))
+    return PointPlan(h.value)
 
 
 # ----------------------------------------------------------------- GPU calls
@@ -315,6 +369,18 @@ def correlator(plans, items, S_u, S_d, precision="p64", use_graph=False, out=Non
     _check(lib().wick_correlator(hp, len(plans), it, len(items), ctypes.c_void_p(S_u.data_ptr()),
                                  ctypes.c_void_p(S_d.data_ptr()), dtype, dims, n_cfg, PRECISIONS[precision],
                                  1 if use_graph else 0, _stream(), ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def point_correlator(p: PointPlan, S_u, S_d, out=None):
+    """Point-sink C [n_cfg, T, 2] float64 on the device (FP64 determinants)."""
+    torch = _torch()
+    n_cfg, T, dims, dtype = _prop_args(S_u, S_d)
+    if out is None:
+        out = torch.empty((n_cfg, T, 2), dtype=torch.float64, device=S_u.device)
+    _check_out(out, (n_cfg, T, 2), S_u.device)
+    _check(lib().wick_point_correlator(p.handle, ctypes.c_void_p(S_u.data_ptr()), ctypes.c_void_p(S_d.data_ptr()),
+                                       dtype, dims, n_cfg, _stream(), ctypes.c_void_p(out.data_ptr())))
     return out
 
 
