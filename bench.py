@@ -40,6 +40,25 @@ WORKLOADS = {
 }
 DEFAULT = "3He-16^3x32"
 
+# point-sink workloads (determinant method): name -> nucleus, dims, seed workload id
+POINT_WORKLOADS = {
+    "point-2H-24^3x8": ("2H", (24, 24, 24, 8), 11),
+    "point-3He-24^3x8": ("3He", (24, 24, 24, 8), 12),
+    "point-4He-24^3x8": ("4He", (24, 24, 24, 8), 13),
+}
+# the paper's point-sink times per time slice at 24^3, seconds (context, other hardware):
+# determinant method B on one i7-12th-gen core (method comparison table of Sec. 3.3)
+# and its CUDA code (timing tables of Sec. 4)
+PAPER_POINT_24 = {"2H": {"method_B_1core": 34.15, "cuda_V100": 0.34, "cuda_A100": 0.15},
+                  "3He": {"method_B_1core": 2754.16, "cuda_V100": 5.24},
+                  "4He": {"method_B_1core": 3246.38, "cuda_V100": 24.72}}
+
+
+def laplace_cmacs(n):
+    """Complex multiply-adds of all minors of one row set: sum_k binom(12, k) k."""
+    from math import comb
+    return sum(comb(12, k) * k for k in range(1, n + 1))
+
 PEAK_TFLOPS = {"p64": 78.6, "p32": 157.3, "pb3": 2500.0, "pb6": 2500.0}
 PEAK_NAME = {"p64": "FP64 MFMA", "p32": "FP32 MFMA", "pb3": "BF16 MFMA", "pb6": "BF16 MFMA"}
 
@@ -83,9 +102,9 @@ def gen_inputs(wid, n_cfg, dims, dtype):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; 3 for point-sink workloads)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(POINT_WORKLOADS))
     ap.add_argument("--precision", default=None, help="p64, p32, pb3, pb6 (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
@@ -109,6 +128,11 @@ def main():
         print(json.dumps({"calibration": "copy", "bytes_read_per_launch": a.numel() * 8,
                           "bytes_written_per_launch": a.numel() * 8, "launches": 5}))
         return
+
+    if args.steps is None:
+        args.steps = 3 if args.workload in POINT_WORKLOADS else 20
+    if args.workload in POINT_WORKLOADS:
+        return point_bench(args)
 
     import torch
     import paper_2411_08962_amd as W
@@ -261,6 +285,101 @@ def main():
     if not args.no_cpu_baseline:
         note("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(items, nuclei, hu, hd, plans, C.cpu().numpy())
+    print(json.dumps(out))
+
+
+def point_bench(args):
+    """Point-sink correlator by determinants (Eq. 2.9, App. A): all time slices
+    of one configuration per step, FP64."""
+    import torch
+    import paper_2411_08962_amd as W
+    nucleus, dims, wid = POINT_WORKLOADS[args.workload]
+    X, Y, Z, T = dims
+    V = X * Y * Z
+    t0 = time.time()
+    hu, hd = gen_inputs(wid, 1, dims, np.complex128)
+    du, dd = torch.from_numpy(hu).cuda(), torch.from_numpy(hd).cuda()
+    pp = W.point_plan_std(nucleus)
+    info = pp.info()
+    note(f"inputs and plan {time.time() - t0:.1f} s")
+    C = torch.empty((1, T, 2), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        W.point_correlator(pp, du, dd, out=C)
+    torch.cuda.synchronize()
+    W.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        W.point_correlator(pp, du, dd, out=C)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    W.profile(False)
+    prof = {k: W.profile_read(k) for k in ("point_minors", "point_pairs", "point_reduce")}
+    step_s = dt / args.steps
+    pairs = info["n_sink_groups"] * info["n_src_groups"]
+    slots = V * T
+    # algorithmic flops per site-slice: minors by Laplace expansion (8 per complex
+    # multiply-add), and 14 per determinant pair (two complex products and an add)
+    f_u = info["n_rows_u"] * laplace_cmacs(info["n_u"]) * 8
+    f_d = info["n_rows_d"] * laplace_cmacs(info["n_d"]) * 8
+    f_p = pairs * 14
+    ms = {k: (v[1] / v[0] if v[0] else None) for k, v in prof.items()}
+    # per step the pairs kernel runs once per chunk: its total time per step
+    t_pairs = prof["point_pairs"][1] / args.steps * 1e-3
+    t_minors = prof["point_minors"][1] / args.steps * 1e-3
+    tf_pairs = (f_u + f_p) * slots / t_pairs / 1e12
+    tf_minors = f_d * slots / t_minors / 1e12
+    roof_pairs = {"bound": "alu", "kernel": "pt_pairs_kernel", "achieved": tf_pairs, "peak": 78.6,
+                  "peak_name": "FP64 vector ALU", "unit": "TFLOP/s", "frac": tf_pairs / 78.6, "traffic": None,
+                  "flops_per_step": (f_u + f_p) * slots, "ms_per_step": t_pairs * 1e3,
+                  "avg_launch_ms": ms["point_pairs"], "launches_per_step": prof["point_pairs"][0] / args.steps}
+    roof_minors = {"bound": "alu", "kernel": "pt_minors_kernel", "achieved": tf_minors, "peak": 78.6,
+                   "peak_name": "FP64 vector ALU", "unit": "TFLOP/s", "frac": tf_minors / 78.6, "traffic": None,
+                   "flops_per_step": f_d * slots, "ms_per_step": t_minors * 1e3, "avg_launch_ms": ms["point_minors"]}
+    out = {
+        "metric": METRIC,
+        "value": pairs * slots / step_s,
+        "unit": "Wick terms/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * step_s,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: point-sink {nucleus} (all quarks of the sink at one site, summed "
+                               f"over sites) by determinants on {X}x{Y}x{Z}x{T}, c128 propagators, FP64, all {T} "
+                               f"time slices; a term is one (sink group, source group) pair of the weighted "
+                               f"double sum at one site",
+                   "lattice": [X, Y, Z, T], "nucleus": nucleus, "plan": info,
+                   "dets_per_site": {"u": info["n_rows_u"] * info["n_cols_u"], "d": info["n_rows_d"] * info["n_cols_d"]}},
+        "roofline": roof_pairs if t_pairs >= t_minors else roof_minors,
+        "rooflines": {"pairs": roof_pairs, "minors": roof_minors},
+        "s_per_time_slice": step_s / T,
+        "paper_s_per_time_slice_24cubed": PAPER_POINT_24.get(nucleus),
+        "kernel_ms": ms,
+    }
+    if not args.no_cpu_baseline:
+        note("cpu baseline (oracle point route)")
+        import oracle
+        from oracle import operators as ops
+        op = ops.by_name(nucleus)
+        su = hu[0].reshape(T, V, 12, 12)
+        sd = hd[0].reshape(T, V, 12, 12)
+        Cg = C.cpu().numpy()[0]
+        t0 = time.perf_counter()
+        n_done, diffs = 0, []
+        # whole time slices while the budget lasts, else a prefix of sites of slice 0
+        for x in range(V):
+            Br = oracle.blocks_raw(op, su[0, x:x + 1], sd[0, x:x + 1])
+            oracle.sum_dp(op, Br)
+            n_done += 1
+            if time.perf_counter() - t0 > 10.0:
+                break
+        dsec = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": pairs * n_done / dsec, "unit": "Wick terms/s", "cores": oracle.threads(),
+                               "kind": "oracle",
+                               "sample": f"{n_done} sites of time slice 0: one-site blocks + subset-DP term sum per "
+                                         f"site (the oracle's point-sink route); value = determinant pairs covered "
+                                         f"per second", "seconds": dsec}
+        if n_done == V:
+            ref = op.scale * sum(oracle.sum_dp(op, oracle.blocks_raw(op, su[0, x:x + 1], sd[0, x:x + 1]))
+                                 for x in range(V))
+            out["cpu_baseline"]["gpu_vs_oracle_rel_diff_t0"] = float(abs(Cg[0, 0] + 1j * Cg[0, 1] - ref) / abs(ref))
     print(json.dumps(out))
 
 

@@ -226,7 +226,7 @@ wick_status wick_autotune(wick_plan_t plan, const int32_t dims[4], wick_dtype dt
  * minimal set of determinants is the set of distinct (row set, column set)
  * pairs per flavor. Uses the same wick_nucleus_desc as wick_plan (the sink
  * patterns are read at one point; kinds need not be nucleon-like). Up to 6
- * quarks of each flavor. */
+ * quarks of each flavor (WICK_EUNSUPPORTED beyond). */
 typedef struct wick_point_s *wick_point_t;
 wick_status wick_point_plan(const wick_nucleus_desc *desc, wick_point_t *out);
 wick_status wick_point_plan_std(const char *nucleus, int32_t J, wick_point_t *out);
@@ -242,7 +242,7 @@ wick_status wick_point_info(wick_point_t plan, int32_t *n_u, int32_t *n_d, int64
  * wick_blocks (device, 16-byte aligned, complex128 or complex64), FP64
  * arithmetic throughout, deterministic. Errors: WICK_EINVAL (null or
  * misaligned pointers, bad sizes), WICK_ENOMEM, WICK_EHIP. Asynchronous on
- * stream. */
+ * stream; the caller keeps S_u, S_d and C alive until it completes. */
 wick_status wick_point_correlator(wick_point_t plan, const void *S_u, const void *S_d, wick_dtype dtype,
                                   const int32_t dims[4], int32_t n_cfg, wick_stream_t stream, double *C);
 void wick_point_destroy(wick_point_t plan);

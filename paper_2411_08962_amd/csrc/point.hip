@@ -43,39 +43,47 @@ constexpr int kPtMaxMinors = 924;   // binom(12, 6)
 constexpr int kPtSubsets = 2509;    // sum_{k=1..6} binom(12, k)
 constexpr int kPtRowsPerWG = 8;     // sink row sets per workgroup
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+__host__ __device__ constexpr int binom12c(int k)
 {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    int r = 1;
+    for (int i = 0; i < k; ++i) r = r * (12 - i) / (i + 1);
+    return r;
+}
+__host__ __device__ constexpr int level_off(int k)
+{
+    int o = 0;
+    for (int i = 1; i < k; ++i) o += binom12c(i);
+    return o;
 }
 
-// Level tables: for level k (1..6) and colex rank r < binom(12, k), entry
-// e = off[k] + r holds the subset's elements and, for each j, the rank of the
-// subset without element j (a (k-1)-subset).
-struct PtSubsets {
-    int32_t off[8];
-    int32_t cnt[8];
-    uint8_t elem[kPtSubsets][6];
-    uint16_t sub[kPtSubsets][6];
+// One subset of level k (1..6), entry level_off(k) + colex rank: its elements
+// (4 bits each) and, for each element j, the colex rank of the subset without
+// it (a (k-1)-subset). 16 bytes, read with one vector load.
+struct alignas(16) PtSubset {
+    uint32_t elems;
+    uint16_t sub[6];
 };
 
 struct PtDev {
     int device = -1;
-    PtSubsets *sub = nullptr;
+    PtSubset *sub = nullptr;
     int8_t *rows_u = nullptr, *rows_d = nullptr;   // [n][8]
     int32_t *u_beg = nullptr, *g_d = nullptr;
     double2 *g_w = nullptr;
-    uint16_t *h_ru = nullptr, *h_cd = nullptr;     // u column rank, d compact column index
-    double2 *h_w = nullptr;
+    uint16_t *h_ru = nullptr;                      // source groups sorted by d column: u column rank
+    double2 *h_w = nullptr;                        // and weight
+    int32_t *cd_beg = nullptr;                     // [n_cd + 1] source groups of each d column
     uint16_t *d_cols = nullptr;                    // compact d column index -> rank
     int n_cd = 0;
 };
 
 struct PtArgs {
-    const PtSubsets *sub;
+    const PtSubset *sub;
     const int8_t *rows_u, *rows_d;
     const int32_t *u_beg, *g_d;
     const double2 *g_w;
-    const uint16_t *h_ru, *h_cd, *d_cols;
+    const uint16_t *h_ru, *d_cols;
+    const int32_t *cd_beg;
     const double2 *h_w;
     int n_u, n_d, n_rows_u, n_rows_d, n_h, n_cd;
     int n_uchunks, n_dchunks;
@@ -84,6 +92,11 @@ struct PtArgs {
     double2 *dd;         // [n_slots][n_rows_d][n_cd]
     double2 *partial;    // [total slots][n_uchunks]
 };
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
 
 __device__ __forceinline__ int xcd_id(int nb)
 {
@@ -98,23 +111,25 @@ __device__ __forceinline__ void stage_site(const TIn *__restrict__ S, int64_t sl
     for (int e = threadIdx.x; e < 144; e += kPtThreads) sS[e] = make_double2((double)p[e].x, (double)p[e].y);
 }
 
-// All minors of rows R[0..n) of the staged 12x12 matrix; returns the LDS
-// buffer that holds level n (binom(12, n) entries by colex rank).
-__device__ double2 *minors(const PtSubsets *__restrict__ T, const double2 *sS, const int8_t *R, int n,
-                           double2 *buf0, double2 *buf1)
+// All minors of rows R[0..N) of the staged 12x12 matrix, level by level;
+// returns the LDS buffer that holds level N (binom(12, N) entries by colex rank).
+template <int N>
+__device__ double2 *minors(const PtSubset *__restrict__ T, const double2 *sS, const int8_t *R, double2 *buf0,
+                           double2 *buf1)
 {
     if (threadIdx.x == 0) buf0[0] = make_double2(1.0, 0.0);
     __syncthreads();
     double2 *prev = buf0, *cur = buf1;
-    for (int k = 1; k <= n; ++k) {
-        const int row = R[k - 1];
-        const int off = T->off[k], cnt = T->cnt[k];
-        for (int r = threadIdx.x; r < cnt; r += kPtThreads) {
-            const uint8_t *el = T->elem[off + r];
-            const uint16_t *sb = T->sub[off + r];
+#pragma unroll
+    for (int k = 1; k <= N; ++k) {
+        const double2 *srow = sS + 12 * R[k - 1];
+        const PtSubset *lev = T + level_off(k);
+        for (int r = threadIdx.x; r < binom12c(k); r += kPtThreads) {
+            const PtSubset e = lev[r];
             double2 s = make_double2(0.0, 0.0);
+#pragma unroll
             for (int j = 0; j < k; ++j) {
-                const double2 t = cmul(sS[row * 12 + el[j]], prev[sb[j]]);
+                const double2 t = cmul(srow[(e.elems >> (4 * j)) & 15], prev[e.sub[j]]);
                 if ((k - 1 + j) & 1) { s.x -= t.x; s.y -= t.y; }
                 else { s.x += t.x; s.y += t.y; }
             }
@@ -128,7 +143,7 @@ __device__ double2 *minors(const PtSubsets *__restrict__ T, const double2 *sS, c
     return prev;
 }
 
-template <typename TIn>
+template <typename TIn, int ND>
 __global__ __launch_bounds__(kPtThreads) void pt_minors_kernel(const TIn *__restrict__ Sd, PtArgs a)
 {
     __shared__ double2 sS[144];
@@ -141,14 +156,22 @@ __global__ __launch_bounds__(kPtThreads) void pt_minors_kernel(const TIn *__rest
     __syncthreads();
     const int r0 = chunk * kPtRowsPerWG, r1 = min(a.n_rows_d, r0 + kPtRowsPerWG);
     for (int r = r0; r < r1; ++r) {
-        const double2 *L = minors(a.sub, sS, a.rows_d + 8 * r, a.n_d, buf[0], buf[1]);
+        const double2 *L = minors<ND>(a.sub, sS, a.rows_d + 8 * r, buf[0], buf[1]);
         double2 *out = a.dd + ((int64_t)slot * a.n_rows_d + r) * a.n_cd;
         for (int c = threadIdx.x; c < a.n_cd; c += kPtThreads) out[c] = L[a.d_cols[c]];
         __syncthreads();
     }
 }
 
-template <typename TIn>
+// The double sum over (sink group g, source group h) is regrouped by the
+// source d column set c: for a sink u row set U,
+//   A_U[c] = sum over source groups h with D'_h = c of W'_h det_u[U; U'_h]
+// (source groups are sorted by c, so each c owns a contiguous range), and
+// every sink group g of U adds W_g sum_c A_U[c] det_d[D_g; c]. Thread t owns
+// the columns c = t + 256 i (i < CS): it builds their A_U[c] from the u minors
+// in LDS, then reads the d determinants of each sink group at its own columns
+// (contiguous across the wave).
+template <typename TIn, int NU, int CS>
 __global__ __launch_bounds__(kPtThreads) void pt_pairs_kernel(const TIn *__restrict__ Su, PtArgs a)
 {
     __shared__ double2 sS[144];
@@ -159,19 +182,41 @@ __global__ __launch_bounds__(kPtThreads) void pt_pairs_kernel(const TIn *__restr
     if (id >= total) return;
     const int slot = id / a.n_uchunks, chunk = id % a.n_uchunks;
     stage_site(Su, a.slot0 + slot, sS);
+    int hb[CS], he[CS];  // source-group range of each owned column (empty past n_cd)
+#pragma unroll
+    for (int i = 0; i < CS; ++i) {
+        const int c = threadIdx.x + kPtThreads * i;
+        hb[i] = c < a.n_cd ? a.cd_beg[c] : 0;
+        he[i] = c < a.n_cd ? a.cd_beg[c + 1] : 0;
+    }
     __syncthreads();
     double2 tot = make_double2(0.0, 0.0);
     const int r0 = chunk * kPtRowsPerWG, r1 = min(a.n_rows_u, r0 + kPtRowsPerWG);
     const double2 *ddslot = a.dd + (int64_t)slot * a.n_rows_d * a.n_cd;
     for (int r = r0; r < r1; ++r) {
-        const double2 *L = minors(a.sub, sS, a.rows_u + 8 * r, a.n_u, buf[0], buf[1]);
+        const double2 *L = minors<NU>(a.sub, sS, a.rows_u + 8 * r, buf[0], buf[1]);
+        double2 av[CS];
+#pragma unroll
+        for (int i = 0; i < CS; ++i) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int h = hb[i]; h < he[i]; ++h) {
+                const double2 t = cmul(a.h_w[h], L[a.h_ru[h]]);
+                acc.x += t.x;
+                acc.y += t.y;
+            }
+            av[i] = acc;
+        }
         for (int g = a.u_beg[r]; g < a.u_beg[r + 1]; ++g) {
             const double2 *drow = ddslot + (int64_t)a.g_d[g] * a.n_cd;
             double2 s = make_double2(0.0, 0.0);
-            for (int h = threadIdx.x; h < a.n_h; h += kPtThreads) {
-                const double2 t = cmul(cmul(a.h_w[h], L[a.h_ru[h]]), drow[a.h_cd[h]]);
-                s.x += t.x;
-                s.y += t.y;
+#pragma unroll
+            for (int i = 0; i < CS; ++i) {
+                const int c = threadIdx.x + kPtThreads * i;
+                if (c < a.n_cd) {
+                    const double2 d = drow[c];
+                    s.x += av[i].x * d.x - av[i].y * d.y;
+                    s.y += av[i].x * d.y + av[i].y * d.x;
+                }
             }
             const double2 t = cmul(a.g_w[g], s);
             tot.x += t.x;
@@ -216,41 +261,28 @@ wick_status pt_hip_fail(hipError_t e, const char *what)
     return fail(WICK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-int64_t binom12(int k)
+void build_subsets(std::vector<PtSubset> &T)
 {
-    int64_t r = 1;
-    for (int i = 0; i < k; ++i) r = r * (12 - i) / (i + 1);
-    return r;
-}
-
-void build_subsets(PtSubsets &T)
-{
-    std::memset(&T, 0, sizeof(T));
-    int e = 0;
-    for (int k = 0; k <= 6; ++k) {
-        T.off[k] = k == 0 ? 0 : e;
-        T.cnt[k] = (int)binom12(k);
-        if (k == 0) continue;
+    T.assign(kPtSubsets, PtSubset{0, {0, 0, 0, 0, 0, 0}});
+    for (int k = 1; k <= 6; ++k) {
         // colex order of k-subsets = increasing bitmask
-        std::vector<int> rank_of(4096, -1);
-        int r = 0;
-        for (int m = 0; m < 4096; ++m)
+        std::vector<int> rank_of(4096, -1), rank_prev(4096, -1);
+        int r = 0, q = 0;
+        for (int m = 0; m < 4096; ++m) {
             if (__builtin_popcount(m) == k) rank_of[m] = r++;
-        std::vector<int> rank_prev(4096, -1);
-        r = 0;
-        for (int m = 0; m < 4096; ++m)
-            if (__builtin_popcount(m) == k - 1) rank_prev[m] = r++;
+            if (__builtin_popcount(m) == k - 1) rank_prev[m] = q++;
+        }
         for (int m = 0; m < 4096; ++m) {
             if (__builtin_popcount(m) != k) continue;
+            PtSubset &e = T[level_off(k) + rank_of[m]];
             int j = 0;
             for (int c = 0; c < 12; ++c)
                 if (m >> c & 1) {
-                    T.elem[e + rank_of[m]][j] = (uint8_t)c;
-                    T.sub[e + rank_of[m]][j] = (uint16_t)rank_prev[m & ~(1 << c)];
+                    e.elems |= (uint32_t)c << (4 * j);
+                    e.sub[j] = (uint16_t)rank_prev[m & ~(1 << c)];
                     ++j;
                 }
         }
-        e += T.cnt[k];
     }
 }
 
@@ -276,7 +308,7 @@ void free_dev(PtDev *d)
     (void)hipFree(d->g_d);
     (void)hipFree(d->g_w);
     (void)hipFree(d->h_ru);
-    (void)hipFree(d->h_cd);
+    (void)hipFree(d->cd_beg);
     (void)hipFree(d->h_w);
     (void)hipFree(d->d_cols);
     delete d;
@@ -292,27 +324,41 @@ wick_status device_tables(wick_point_s *p, PtDev **out)
         if (((PtDev *)v)->device == dev) { *out = (PtDev *)v; return WICK_OK; }
     auto d = new PtDev();
     d->device = dev;
-    PtSubsets T;
-    build_subsets(T);
-    std::vector<PtSubsets> tv(1, T);
+    std::vector<PtSubset> tv;
+    build_subsets(tv);
     std::vector<int8_t> ru, rd;
     for (auto &r : p->rows_u) ru.insert(ru.end(), r.begin(), r.end());
     for (auto &r : p->rows_d) rd.insert(rd.end(), r.begin(), r.end());
-    std::vector<double2> gw(p->g_u.size()), hw(p->h_ru.size());
+    std::vector<double2> gw(p->g_u.size());
     for (size_t i = 0; i < gw.size(); ++i) gw[i] = make_double2(p->g_w[2 * i], p->g_w[2 * i + 1]);
-    for (size_t i = 0; i < hw.size(); ++i) hw[i] = make_double2(p->h_w[2 * i], p->h_w[2 * i + 1]);
-    // compact d columns: the source column sets that occur
+    // compact d columns: the source column sets that occur, in rank order
     std::map<int, int> cols;
     for (uint16_t r : p->h_rd) cols.emplace(r, 0);
-    std::vector<uint16_t> dcols, hcd(p->h_rd.size());
+    std::vector<uint16_t> dcols;
     for (auto &c : cols) { c.second = (int)dcols.size(); dcols.push_back((uint16_t)c.first); }
-    for (size_t i = 0; i < hcd.size(); ++i) hcd[i] = (uint16_t)cols[p->h_rd[i]];
     d->n_cd = (int)dcols.size();
+    // source groups ordered by (d column, u column), with the range of each d column
+    const size_t H = p->h_ru.size();
+    std::vector<size_t> ord(H);
+    for (size_t i = 0; i < H; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
+        return p->h_rd[x] != p->h_rd[y] ? p->h_rd[x] < p->h_rd[y] : p->h_ru[x] < p->h_ru[y];
+    });
+    std::vector<uint16_t> hru(H);
+    std::vector<double2> hw(H);
+    std::vector<int32_t> cdb(d->n_cd + 1, 0);
+    for (size_t i = 0; i < H; ++i) {
+        const size_t h = ord[i];
+        hru[i] = p->h_ru[h];
+        hw[i] = make_double2(p->h_w[2 * h], p->h_w[2 * h + 1]);
+        cdb[cols[p->h_rd[h]] + 1]++;
+    }
+    for (int c = 0; c < d->n_cd; ++c) cdb[c + 1] += cdb[c];
     wick_status st;
     if ((st = upload(tv, &d->sub)) != WICK_OK || (st = upload(ru, &d->rows_u)) != WICK_OK ||
         (st = upload(rd, &d->rows_d)) != WICK_OK || (st = upload(p->u_beg, &d->u_beg)) != WICK_OK ||
         (st = upload(p->g_d, &d->g_d)) != WICK_OK || (st = upload(gw, &d->g_w)) != WICK_OK ||
-        (st = upload(p->h_ru, &d->h_ru)) != WICK_OK || (st = upload(hcd, &d->h_cd)) != WICK_OK ||
+        (st = upload(hru, &d->h_ru)) != WICK_OK || (st = upload(cdb, &d->cd_beg)) != WICK_OK ||
         (st = upload(hw, &d->h_w)) != WICK_OK || (st = upload(dcols, &d->d_cols)) != WICK_OK) {
         free_dev(d);
         return st;
@@ -350,7 +396,7 @@ wick_status launch_point(wick_point_s *p, PtDev *d, const TIn *Su, const TIn *Sd
     a.g_d = d->g_d;
     a.g_w = d->g_w;
     a.h_ru = d->h_ru;
-    a.h_cd = d->h_cd;
+    a.cd_beg = d->cd_beg;
     a.d_cols = d->d_cols;
     a.h_w = d->h_w;
     a.n_u = p->n_u;
@@ -377,11 +423,25 @@ wick_status launch_point(wick_point_s *p, PtDev *d, const TIn *Su, const TIn *Sd
         a.slot0 = s0;
         a.n_slots = (int)std::min<int64_t>(chunk, slots - s0);
         const int64_t nd = (int64_t)a.n_slots * a.n_dchunks, nu = (int64_t)a.n_slots * a.n_uchunks;
+        const dim3 gd((unsigned)((nd + 7) / 8 * 8)), gu((unsigned)((nu + 7) / 8 * 8)), blk(kPtThreads);
         Probe pa("point_minors", s);
-        pt_minors_kernel<TIn><<<dim3((unsigned)((nd + 7) / 8 * 8)), dim3(kPtThreads), 0, s>>>(Sd, a);
+        switch (a.n_d) {
+#define PT_MINORS(n) case n: pt_minors_kernel<TIn, n><<<gd, blk, 0, s>>>(Sd, a); break;
+            PT_MINORS(0) PT_MINORS(1) PT_MINORS(2) PT_MINORS(3) PT_MINORS(4) PT_MINORS(5) PT_MINORS(6)
+#undef PT_MINORS
+        }
         pa.stop();
         Probe pb("point_pairs", s);
-        pt_pairs_kernel<TIn><<<dim3((unsigned)((nu + 7) / 8 * 8)), dim3(kPtThreads), 0, s>>>(Su, a);
+        const int cs = (a.n_cd + kPtThreads - 1) / kPtThreads;  // 1..4 (n_cd <= 924)
+        switch (a.n_u * 4 + cs - 1) {
+#define PT_PAIRS(n)                                                                \
+    case 4 * n + 0: pt_pairs_kernel<TIn, n, 1><<<gu, blk, 0, s>>>(Su, a); break;  \
+    case 4 * n + 1: pt_pairs_kernel<TIn, n, 2><<<gu, blk, 0, s>>>(Su, a); break;  \
+    case 4 * n + 2: pt_pairs_kernel<TIn, n, 3><<<gu, blk, 0, s>>>(Su, a); break;  \
+    case 4 * n + 3: pt_pairs_kernel<TIn, n, 4><<<gu, blk, 0, s>>>(Su, a); break;
+            PT_PAIRS(0) PT_PAIRS(1) PT_PAIRS(2) PT_PAIRS(3) PT_PAIRS(4) PT_PAIRS(5) PT_PAIRS(6)
+#undef PT_PAIRS
+        }
         pb.stop();
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return pt_hip_fail(e, "point kernels");
