@@ -212,6 +212,44 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
 wick_status wick_autotune(wick_plan_t plan, const int32_t dims[4], wick_dtype dtype,
                           wick_precision prec, const char *cache_path);
 
+/* ------------------------------------------------- correlation matrices */
+
+/* Correlation matrix for the generalized eigenvalue problem (Eqs. E1-E3):
+ * C_ij(t) with operator i at the sink and operator j at the source, for
+ * n_ops <= 4 operators that share A and flavor content (each desc as for
+ * wick_plan; element (i, j) is normalised by sqrt(scale_i * scale_j), scales
+ * must be positive). Every element is planned like wick_plan; the element
+ * tables are united into one table whose terms are distinct block-entry
+ * monomials with one coefficient per element, so a monomial shared by
+ * several elements is evaluated once (the cross-element common
+ * sub-expressions of Sec. E). Host only; errors as wick_plan. */
+typedef struct wick_gevp_s *wick_gevp_t;
+wick_status wick_gevp_plan(const wick_nucleus_desc *ops, int32_t n_ops, wick_gevp_t *out);
+
+/* Sizes: operators, A, block kinds, terms of the union table, and the sum of
+ * the element tables' sizes. */
+wick_status wick_gevp_info(wick_gevp_t plan, int32_t *n_ops, int32_t *A, int32_t *n_kinds, int64_t *n_terms,
+                           int64_t *n_element_terms);
+
+/* Copy the union table out: kidx[A][n_terms] as for wick_plan_table (each
+ * term's indices ascending), coef[n_terms][n_ops * n_ops][2] (element
+ * e = i * n_ops + j; zero where the term does not occur). */
+wick_status wick_gevp_table(wick_gevp_t plan, uint16_t *kidx, double *coef);
+
+/* A borrowed plan handle with the matrix's block kinds and no terms, valid
+ * while the GEVP plan lives (do not destroy it): use it with wick_blocks
+ * (the blocks of every element at once), wick_plan_kind and wick_autotune. */
+wick_status wick_gevp_kinds(wick_gevp_t plan, wick_plan_t *blocks_plan);
+
+/* C[cfg][t][i][j][2] (device double) = sum over union terms of
+ * coef[n][i * n_ops + j] * prod_a B[cfg][t][kidx_{a,n}], FP64, deterministic;
+ * B as written by wick_blocks for the wick_gevp_kinds plan. Errors:
+ * WICK_EINVAL (null or misaligned pointers, bad sizes), WICK_ENOMEM,
+ * WICK_EHIP. Asynchronous on stream. */
+wick_status wick_gevp_contract(wick_gevp_t plan, const double *B, int32_t n_cfg, int32_t T,
+                               wick_stream_t stream, double *C);
+void wick_gevp_destroy(wick_gevp_t plan);
+
 /* ------------------------------------------------------- point sinks */
 
 /* Point-sink correlators by the determinant method (Sec. 3.1 Eq. 2.9,

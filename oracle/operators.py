@@ -109,17 +109,21 @@ def proton_pair(alpha_snk, alpha_src, proj=0):
                     f"p{alpha_snk}{alpha_src}")
 
 
-def deuteron():
-    """O_2H = n^T (C g5 P_+) p with unprojected p, n (Sec. 3.3, deuteron operator)."""
+def deuteron(proj=+1):
+    """O_2H = n^T (C g5 P_+) p with unprojected p, n (Sec. 3.3, deuteron operator).
+
+    proj = -1 puts P_- in place of P_+ and proj = 0 drops the projector: the
+    same block kinds with other couplings, a basis for a correlation matrix.
+    """
     kt = _KindTable()
-    M = cv.cg5() @ cv.proj(+1)
+    M = cv.cg5() @ cv.proj(proj) if proj else cv.cg5()
     pats = []
     for beta in range(4):
         for alpha in range(4):
             c = int(M[beta, alpha])
             if c:
                 pats.append(((kt.get("n", 0, beta), kt.get("p", 0, alpha)), (c, 0)))
-    return Operator(2, kt.kinds, pats, list(pats), 1.0, "2H")
+    return Operator(2, kt.kinds, pats, list(pats), 1.0, "2H" if proj == 1 else f"2H({proj:+d})")
 
 
 def _three_body(first, mid, last, J):

@@ -4,6 +4,7 @@ contraction with baryon blocks (arXiv 2411.08962).
 The C ABI is in ``include/wick.h``; :mod:`.wick` is its Python binding.
 """
 from .wick import (BLOCK_LEN, ECORRUPT, EHIP, EINVAL, ENOMEM, EUNSUPPORTED, ETOOBIG, EXPORTS, OK,  # noqa: F401
-                   PRECISIONS, Plan, PointPlan, WickError, autotune, blocks,
-                   contract, correlator, lib, plan, plan_std, point_correlator, point_plan, point_plan_std,
+                   PRECISIONS, GevpPlan, Plan, PointPlan, WickError, autotune, blocks,
+                   contract, correlator, gevp_contract, gevp_plan, lib, plan, plan_std, point_correlator,
+                   point_plan, point_plan_std,
                    profile, profile_read, version)

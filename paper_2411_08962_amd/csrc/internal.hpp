@@ -103,6 +103,20 @@ struct wick_point_s {
     ~wick_point_s();
 };
 
+// A correlation matrix for the GEVP (Eqs. E1-E3): the union of the element
+// tables, one coefficient per element and term.
+struct wick_gevp_s {
+    int n_ops = 0, A = 0;
+    int64_t n_terms = 0, n_element_terms = 0;
+    std::vector<uint16_t> kidx;   // [A][n_terms], kind * 792 + compact index, tuple sorted
+    std::vector<double> coef;     // [n_terms][n_ops * n_ops][2], normalisation included
+    bool coef_real = true;
+    wick_plan_t carrier = nullptr;  // block kinds, no terms (drives the block kernels)
+    std::mutex dev_mu;
+    std::vector<void *> dev;      // device tables, one per device (gevp.hip)
+    ~wick_gevp_s();
+};
+
 namespace wick {
 
 void set_error(const std::string &msg);
@@ -122,6 +136,10 @@ wick_status truncate_plan(const wick_plan_s *p, const double *B_cal, int32_t n_s
 // built-in operators (nuclei.cpp)
 wick_status std_plan(const char *name, int32_t J, wick_plan_t *out);
 wick_status std_point_plan(const char *name, int32_t J, wick_point_t *out);
+
+// GEVP union plan (gevp.cpp) and device tables (gevp.hip)
+wick_status build_gevp(const wick_nucleus_desc *ops, int32_t n_ops, wick_gevp_t *out);
+void release_gevp_tables(wick_gevp_s *g);
 
 // point-sink planner (point.cpp) and device tables (point.hip)
 wick_status build_point_plan(const wick_nucleus_desc *d, wick_point_t *out);

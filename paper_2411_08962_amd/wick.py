@@ -51,7 +51,8 @@ EXPORTS = ["wick_plan", "wick_plan_std", "wick_plan_info", "wick_plan_stats", "w
            "wick_plan_kind", "wick_plan_save", "wick_plan_load", "wick_plan_truncate", "wick_plan_destroy", "wick_blocks",
            "wick_contract", "wick_correlator", "wick_autotune", "wick_shutdown", "wick_last_error",
            "wick_version", "wick_profile", "wick_profile_read", "wick_point_plan", "wick_point_plan_std",
-           "wick_point_info", "wick_point_correlator", "wick_point_destroy"]
+           "wick_point_info", "wick_point_correlator", "wick_point_destroy", "wick_gevp_plan", "wick_gevp_info",
+           "wick_gevp_table", "wick_gevp_kinds", "wick_gevp_contract", "wick_gevp_destroy"]
 
 _lib = None
 
@@ -89,6 +90,14 @@ def lib():
     L.wick_point_plan_std.argtypes = [ctypes.c_char_p, i32, pp]
     L.wick_point_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)] + [ctypes.POINTER(i64)] * 6
     L.wick_point_correlator.argtypes = [P, P, P, st, P, i32, P, P]
+    L.wick_gevp_plan.argtypes = [ctypes.POINTER(_Desc), i32, pp]
+    L.wick_gevp_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                 ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.wick_gevp_table.argtypes = [P, P, P]
+    L.wick_gevp_kinds.argtypes = [P, pp]
+    L.wick_gevp_contract.argtypes = [P, P, i32, i32, P, P]
+    L.wick_gevp_destroy.argtypes = [P]
+    L.wick_gevp_destroy.restype = None
     L.wick_point_destroy.argtypes = [P]
     L.wick_point_destroy.restype = None
     L.wick_last_error.restype = ctypes.c_char_p
@@ -97,7 +106,8 @@ def lib():
                  "wick_plan_kind", "wick_plan_save", "wick_plan_load", "wick_plan_truncate", "wick_blocks",
                  "wick_contract",
                  "wick_correlator", "wick_autotune", "wick_shutdown", "wick_profile", "wick_profile_read",
-                 "wick_point_plan", "wick_point_plan_std", "wick_point_info", "wick_point_correlator"):
+                 "wick_point_plan", "wick_point_plan_std", "wick_point_info", "wick_point_correlator",
+                 "wick_gevp_plan", "wick_gevp_info", "wick_gevp_table", "wick_gevp_kinds", "wick_gevp_contract"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -275,6 +285,85 @@ class PointPlan:
         out = {"n_u": nu.value, "n_d": nd.value}
         out.update({k: x.value for k, x in zip(keys, v)})
         return out
+
+
+class _BorrowedPlan(Plan):
+    """A plan handle owned by another object (never destroyed here)."""
+
+    def __init__(self, handle, owner):
+        super().__init__(handle)
+        self._owner = owner
+
+    def __del__(self):
+        pass
+
+
+class GevpPlan:
+    """An N x N correlation-matrix plan (owned by the library)."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.wick_gevp_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def info(self):
+        n, A, K = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        N, Ne = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().wick_gevp_info(self._h, *[ctypes.byref(x) for x in (n, A, K, N, Ne)]))
+        return {"n_ops": n.value, "A": A.value, "n_kinds": K.value, "n_terms": N.value, "n_element_terms": Ne.value}
+
+    def table(self):
+        """(kidx [A, N] uint16, coef [N, n_ops, n_ops] complex128)."""
+        i = self.info()
+        A, N, n = i["A"], i["n_terms"], i["n_ops"]
+        kidx = np.zeros((A, N), dtype=np.uint16)
+        coef = np.zeros((N, n * n, 2), dtype=np.float64)
+        _check(lib().wick_gevp_table(self._h, kidx.ctypes.data_as(ctypes.c_void_p), coef.ctypes.data_as(ctypes.c_void_p)))
+        return kidx, (coef[..., 0] + 1j * coef[..., 1]).reshape(N, n, n)
+
+    def blocks_plan(self):
+        """The borrowed plan with the matrix's block kinds (for blocks(), autotune(), kind())."""
+        h = ctypes.c_void_p()
+        _check(lib().wick_gevp_kinds(self._h, ctypes.byref(h)))
+        return _BorrowedPlan(h.value, self)
+
+
+def gevp_plan(ops):
+    """Correlation-matrix plan of operators given as dicts of plan() arguments."""
+    descs = (_Desc * len(ops))()
+    keep = []
+    for i, o in enumerate(ops):
+        d, k = _desc(**o)
+        descs[i] = d
+        keep.append(k)
+    h = ctypes.c_void_p()
+    _check(lib().wick_gevp_plan(descs, len(ops), ctypes.byref(h)))
+    return GevpPlan(h.value)
+
+
+def gevp_contract(g: GevpPlan, B, out=None):
+    """C [n_cfg, T, n_ops, n_ops, 2] float64 from blocks of g.blocks_plan()."""
+    torch = _torch()
+    i = g.info()
+    n = i["n_ops"]
+    if not B.is_cuda or not B.is_contiguous() or B.dtype != torch.float64 or B.dim() != 5:
+        raise ValueError("B must be a contiguous float64 device tensor [n_cfg, T, K, 792, 2]")
+    if B.shape[2:] != (i["n_kinds"], BLOCK_LEN, 2):
+        raise ValueError("B does not match the matrix's block kinds")
+    n_cfg, T = B.shape[:2]
+    if out is None:
+        out = torch.empty((n_cfg, T, n, n, 2), dtype=torch.float64, device=B.device)
+    _check_out(out, (n_cfg, T, n, n, 2), B.device)
+    _check(lib().wick_gevp_contract(g.handle, ctypes.c_void_p(B.data_ptr()), n_cfg, T, _stream(),
+                                    ctypes.c_void_p(out.data_ptr())))
+    return out
 
 
 def point_plan(A, kinds, snk, src, scale=1.0):
