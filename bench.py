@@ -46,6 +46,11 @@ POINT_WORKLOADS = {
     "point-3He-24^3x8": ("3He", (24, 24, 24, 8), 12),
     "point-4He-24^3x8": ("4He", (24, 24, 24, 8), 13),
 }
+# correlation-matrix workloads (GEVP): name -> basis, dims, seed workload id
+GEVP_WORKLOADS = {
+    "gevp-2H-16^3x32": ("2H: n^T C g5 P+ p, n^T C g5 P- p, n^T C g5 p", (16, 16, 16, 32), 21),
+}
+
 # the paper's point-sink times per time slice at 24^3, seconds (context, other hardware):
 # determinant method B on one i7-12th-gen core (method comparison table of Sec. 3.3)
 # and its CUDA code (timing tables of Sec. 4)
@@ -104,7 +109,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; 3 for point-sink workloads)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(POINT_WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT,
+                    choices=sorted(WORKLOADS) + sorted(POINT_WORKLOADS) + sorted(GEVP_WORKLOADS))
     ap.add_argument("--precision", default=None, help="p64, p32, pb3, pb6 (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
@@ -133,6 +139,8 @@ def main():
         args.steps = 3 if args.workload in POINT_WORKLOADS else 20
     if args.workload in POINT_WORKLOADS:
         return point_bench(args)
+    if args.workload in GEVP_WORKLOADS:
+        return gevp_bench(args)
 
     import torch
     import paper_2411_08962_amd as W
@@ -285,6 +293,112 @@ def main():
     if not args.no_cpu_baseline:
         note("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(items, nuclei, hu, hd, plans, C.cpu().numpy())
+    print(json.dumps(out))
+
+
+def gevp_bench(args):
+    """Correlation matrix of three deuteron operators (Eqs. E1-E3): blocks of the
+    matrix's kinds and the union term sum per step; beside it, the nine elements
+    as nine separate correlators (one batched call)."""
+    import torch
+    import paper_2411_08962_amd as W
+    desc, dims, wid = GEVP_WORKLOADS[args.workload]
+    X, Y, Z, T = dims
+    V = X * Y * Z
+    names = ["2H", "2H-", "2H0"]
+    n = len(names)
+    hu, hd = gen_inputs(wid, 1, dims, np.complex128)
+    du, dd = torch.from_numpy(hu).cuda(), torch.from_numpy(hd).cuda()
+    t0 = time.time()
+    g = W.gevp_plan_std(names)
+    t_plan = time.time() - t0
+    info = g.info()
+    bp = g.blocks_plan()
+    B = torch.empty((1, T, info["n_kinds"], W.BLOCK_LEN, 2), dtype=torch.float64, device="cuda")
+    C = torch.empty((1, T, n, n, 2), dtype=torch.float64, device="cuda")
+
+    def step():
+        W.blocks(bp, du, dd, out=B)
+        W.gevp_contract(g, B, out=C)
+
+    elems = [W.plan_std_pair(names[i], names[j]) for i in range(n) for j in range(n)]
+    Ce = torch.empty((n * n, T, 2), dtype=torch.float64, device="cuda")
+
+    def step_elements():
+        W.correlator(elems, [(e, 0) for e in range(n * n)], du, dd, use_graph=True, out=Ce)
+
+    def timed(f):
+        for _ in range(args.warmup):
+            f()
+        torch.cuda.synchronize()
+        W.profile(True)
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            f()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / args.steps
+        W.profile(False)
+        return dt
+
+    dt = timed(step)
+    prof = {k: W.profile_read(k) for k in ("blocks", "blocks_reduce", "gevp_contract")}
+    dt_e = timed(step_elements)
+    Cm = C.cpu().numpy()[0]
+    Cs = Ce.cpu().numpy()
+    dev = max(abs(complex(*Cm[t, i, j]) - complex(*Cs[i * n + j, t])) / max(abs(complex(*Cs[i * n + j, t])), 1e-300)
+              for i in range(n) for j in range(n) for t in range(T))
+    nb, msb = prof["blocks"]
+    nc, msc = prof["gevp_contract"]
+    avg_b, avg_c = msb / max(nb, 1), msc / max(nc, 1)
+    flops_b = block_flops_per_site("2H") * info["n_kinds"] / KINDS["2H"] * V * T
+    tf_b = flops_b / (avg_b * 1e-3) / 1e12
+    E = n * n
+    sum_flops = info["n_terms"] * T * (6 * (info["A"] - 1) + 4 * E)
+    tf_c = sum_flops / (avg_c * 1e-3) / 1e12
+    roof_b = {"bound": "mfma", "kernel": "blocks_nucleon_kernel", "achieved": tf_b, "peak": 78.6,
+              "peak_name": "FP64 MFMA", "unit": "TFLOP/s", "frac": tf_b / 78.6, "traffic": None,
+              "flops_per_launch": flops_b, "avg_launch_ms": avg_b}
+    roof_c = {"bound": "alu", "kernel": "gevp_contract_kernel", "achieved": tf_c, "peak": 78.6,
+              "peak_name": "FP64 vector ALU", "unit": "TFLOP/s", "frac": tf_c / 78.6, "traffic": None,
+              "flops_per_launch": sum_flops, "avg_launch_ms": avg_c}
+    out = {
+        "metric": METRIC,
+        "value": info["n_element_terms"] * T / dt,
+        "unit": "Wick terms/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {n}x{n} correlation matrix of {desc} on {X}x{Y}x{Z}x{T}, c128, "
+                               f"FP64, all {T} time slices; value = element-table terms covered per second",
+                   "lattice": [X, Y, Z, T], "plan": info, "plan_s": t_plan},
+        "roofline": roof_b if avg_b >= avg_c else roof_c,
+        "rooflines": {"blocks": roof_b, "union_term_sum": roof_c},
+        "elementwise": {"ms_per_step": 1e3 * dt_e, "how": f"{n * n} element plans as one batched correlator call "
+                                                          f"(graph), each element with its own blocks",
+                        "speedup_of_union": dt_e / dt, "max_rel_diff_vs_union": float(dev)},
+        "kernel_ms": {"blocks": avg_b, "gevp_contract": avg_c},
+    }
+    if not args.no_cpu_baseline:
+        note("cpu baseline (oracle, element by element)")
+        import oracle
+        from oracle import operators as ops
+        sys.path.insert(0, ROOT)
+        from tests.helpers import gevp_element
+        op_list = [ops.deuteron(+1), ops.deuteron(-1), ops.deuteron(0)]
+        t0 = time.perf_counter()
+        done = 0
+        for t in range(T):
+            for i in range(n):
+                for j in range(n):
+                    el = gevp_element(op_list, i, j)
+                    oracle.sum_dp(el, oracle.blocks_raw(el, hu[0, t], hd[0, t]))
+            done += 1
+            if time.perf_counter() - t0 > 10.0:
+                break
+        dsec = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": info["n_element_terms"] * done / dsec, "unit": "Wick terms/s",
+                               "cores": oracle.threads(), "kind": "oracle",
+                               "sample": f"{done} time slices x {n * n} elements: oracle blocks + subset-DP term sum",
+                               "seconds": dsec}
     print(json.dumps(out))
 
 

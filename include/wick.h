@@ -114,9 +114,17 @@ typedef struct {
 wick_status wick_plan(const wick_nucleus_desc *desc, wick_plan_t *out);
 
 /* Built-in operators of Sec. 3.3: "1H" (proton, spin J), "2H", "3He",
- * "3H", "4He". J is the spin of the last nucleon where the operator has one
+ * "3H", "4He"; also "2H-" and "2H0" (the deuteron operator with P_- and with
+ * no projector). J is the spin of the last nucleon where the operator has one
  * (3He, 3H) or the proton's sink and source spin (1H); ignored otherwise. */
 wick_status wick_plan_std(const char *nucleus, int32_t J, wick_plan_t *out);
+
+/* An off-diagonal correlator of built-in operators: `sink` (spin J_sink) at
+ * the sink and `source` (spin J_source) at the source, normalised by
+ * sqrt(scale_sink * scale_source); one element of a correlation matrix
+ * (Eq. E1) planned on its own. */
+wick_status wick_plan_std_pair(const char *sink, int32_t J_sink, const char *source, int32_t J_source,
+                               wick_plan_t *out);
 
 /* Sizes: A, number of block kinds, number of terms. */
 wick_status wick_plan_info(wick_plan_t plan, int32_t *A, int32_t *n_kinds, int64_t *n_terms);
@@ -225,6 +233,11 @@ wick_status wick_autotune(wick_plan_t plan, const int32_t dims[4], wick_dtype dt
  * sub-expressions of Sec. E). Host only; errors as wick_plan. */
 typedef struct wick_gevp_s *wick_gevp_t;
 wick_status wick_gevp_plan(const wick_nucleus_desc *ops, int32_t n_ops, wick_gevp_t *out);
+
+/* The same for built-in operators (names as for wick_plan_std, spins J[i]
+ * or all 0 if J is NULL); "2H-" and "2H0" are the deuteron operator with P_-
+ * and with no projector, a basis with "2H". */
+wick_status wick_gevp_plan_std(const char *const *names, const int32_t *J, int32_t n_ops, wick_gevp_t *out);
 
 /* Sizes: operators, A, block kinds, terms of the union table, and the sum of
  * the element tables' sizes. */

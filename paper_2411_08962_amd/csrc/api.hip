@@ -1160,6 +1160,11 @@ wick_status wick_plan(const wick_nucleus_desc *desc, wick_plan_t *out) { WICK_TR
 
 wick_status wick_plan_std(const char *nucleus, int32_t J, wick_plan_t *out) { WICK_TRY(return std_plan(nucleus, J, out)); }
 
+wick_status wick_plan_std_pair(const char *sink, int32_t J_sink, const char *source, int32_t J_source, wick_plan_t *out)
+{
+    WICK_TRY(return std_pair_plan(sink, J_sink, source, J_source, out));
+}
+
 wick_status wick_plan_info(wick_plan_t p, int32_t *A, int32_t *n_kinds, int64_t *n_terms)
 {
     if (!p) return fail(WICK_EINVAL, "wick_plan_info: null plan");

@@ -227,6 +227,17 @@ wick_status wick_gevp_plan(const wick_nucleus_desc *ops, int32_t n_ops, wick_gev
     }
 }
 
+wick_status wick_gevp_plan_std(const char *const *names, const int32_t *J, int32_t n_ops, wick_gevp_t *out)
+{
+    try {
+        return std_gevp_plan(names, J, n_ops, out);
+    } catch (const std::bad_alloc &) {
+        return fail(WICK_ENOMEM, "wick_gevp_plan_std: out of host memory");
+    } catch (const std::exception &ex) {
+        return fail(WICK_EINVAL, std::string("wick_gevp_plan_std: internal: ") + ex.what());
+    }
+}
+
 wick_status wick_gevp_info(wick_gevp_t g, int32_t *n_ops, int32_t *A, int32_t *n_kinds, int64_t *n_terms,
                            int64_t *n_element_terms)
 {

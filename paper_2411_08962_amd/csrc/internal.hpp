@@ -136,6 +136,8 @@ wick_status truncate_plan(const wick_plan_s *p, const double *B_cal, int32_t n_s
 // built-in operators (nuclei.cpp)
 wick_status std_plan(const char *name, int32_t J, wick_plan_t *out);
 wick_status std_point_plan(const char *name, int32_t J, wick_point_t *out);
+wick_status std_gevp_plan(const char *const *names, const int32_t *J, int32_t n_ops, wick_gevp_t *out);
+wick_status std_pair_plan(const char *snk, int32_t J_snk, const char *src, int32_t J_src, wick_plan_t *out);
 
 // GEVP union plan (gevp.cpp) and device tables (gevp.hip)
 wick_status build_gevp(const wick_nucleus_desc *ops, int32_t n_ops, wick_gevp_t *out);

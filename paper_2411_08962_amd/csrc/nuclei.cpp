@@ -8,6 +8,8 @@
 // Nucleon kind (Eqs. 2.2-2.3, projected forms of Sec. 3.3): the proton
 // p_alpha = eps_abc u^a_alpha u^b_beta (C g5 Q)_{beta eta} d^c_eta, quark
 // slots listed as (u^a_alpha, d^c_eta, u^b_beta); the neutron swaps u and d.
+#include <algorithm>
+#include <cmath>
 #include <complex>
 #include <cstring>
 #include <string>
@@ -131,11 +133,11 @@ struct OpBuilder {
         re.push_back(c);
         im.push_back(0);
     }
-    // The operator as a wick_nucleus_desc (valid during the call of f).
-    template <class F>
-    wick_status with_desc(F &&f)
+    std::vector<wick_kind> wk;
+    // The operator as a wick_nucleus_desc (valid while the builder lives and is unchanged).
+    wick_nucleus_desc desc()
     {
-        std::vector<wick_kind> wk(kinds.size());
+        wk.assign(kinds.size(), wick_kind{});
         for (size_t i = 0; i < kinds.size(); ++i) {
             for (int s = 0; s < 3; ++s) wk[i].flavor[s] = kinds[i].flav[s];
             wk[i].n_w = (int32_t)kinds[i].re.size();
@@ -152,7 +154,7 @@ struct OpBuilder {
         d.snk_re = d.src_re = re.data();
         d.snk_im = d.src_im = im.data();
         d.scale = scale;
-        return f(&d);
+        return d;
     }
 };
 
@@ -170,10 +172,11 @@ wick_status std_operator(const char *name, int32_t J, OpBuilder &ob)
         if (J < 0 || J > 3) return fail(WICK_EINVAL, "wick_plan_std: J must be 0..3");
         ob.A = 1;
         ob.pattern({ob.kind('p', 0, J)}, 1);
-    } else if (n == "2H") {
-        // O_2H = n^T (C g5 P_+) p, unprojected nucleons
+    } else if (n == "2H" || n == "2H-" || n == "2H0") {
+        // O_2H = n^T (C g5 P_+) p, unprojected nucleons; "2H-" has P_- and "2H0"
+        // no projector (the same block kinds: a basis for a correlation matrix)
         ob.A = 2;
-        M4 M = mat_mul(basis().cg5, basis().pp);
+        M4 M = n == "2H0" ? basis().cg5 : mat_mul(basis().cg5, n == "2H" ? basis().pp : basis().pm);
         for (int b = 0; b < 4; ++b)
             for (int a = 0; a < 4; ++a)
                 if (M[b][a] != cx(0, 0)) ob.pattern({ob.kind('n', 0, b), ob.kind('p', 0, a)}, M[b][a].real());
@@ -202,7 +205,7 @@ wick_status std_operator(const char *name, int32_t J, OpBuilder &ob)
                 ob.pattern({k[0], k[1], k[2], k[3]}, c);
             }
     } else {
-        return fail(WICK_EINVAL, "wick_plan_std: unknown nucleus '" + n + "' (1H, 2H, 3He, 3H, 4He)");
+        return fail(WICK_EINVAL, "wick_plan_std: unknown nucleus '" + n + "' (1H, 2H, 2H-, 2H0, 3He, 3H, 4He)");
     }
     return WICK_OK;
 }
@@ -215,7 +218,8 @@ wick_status std_plan(const char *name, int32_t J, wick_plan_t *out)
     OpBuilder ob;
     wick_status st = std_operator(name, J, ob);
     if (st != WICK_OK) return st;
-    return ob.with_desc([&](const wick_nucleus_desc *d) { return build_plan(d, out); });
+    const wick_nucleus_desc d = ob.desc();
+    return build_plan(&d, out);
 }
 
 wick_status std_point_plan(const char *name, int32_t J, wick_point_t *out)
@@ -224,7 +228,52 @@ wick_status std_point_plan(const char *name, int32_t J, wick_point_t *out)
     OpBuilder ob;
     wick_status st = std_operator(name, J, ob);
     if (st != WICK_OK) return st;
-    return ob.with_desc([&](const wick_nucleus_desc *d) { return build_point_plan(d, out); });
+    const wick_nucleus_desc d = ob.desc();
+    return build_point_plan(&d, out);
+}
+
+wick_status std_pair_plan(const char *snk, int32_t J_snk, const char *src, int32_t J_src, wick_plan_t *out)
+{
+    if (!out) return fail(WICK_EINVAL, "wick_plan_std_pair: null argument");
+    OpBuilder a, b;
+    wick_status st = std_operator(snk, J_snk, a);
+    if (st != WICK_OK) return st;
+    if ((st = std_operator(src, J_src, b)) != WICK_OK) return st;
+    if (a.A != b.A) return fail(WICK_EINVAL, "wick_plan_std_pair: the operators differ in A");
+    // the source's kinds joined to the sink's (kinds are keyed by type, projector and spin)
+    std::vector<int32_t> src_kind;
+    std::vector<int> bmap;
+    for (size_t i = 0; i < b.kinds.size(); ++i) {
+        auto it = std::find(a.keys.begin(), a.keys.end(), b.keys[i]);
+        if (it == a.keys.end()) {
+            a.keys.push_back(b.keys[i]);
+            a.kinds.push_back(b.kinds[i]);
+            bmap.push_back((int)a.kinds.size() - 1);
+        } else {
+            bmap.push_back((int)(it - a.keys.begin()));
+        }
+    }
+    for (int32_t k : b.pk) src_kind.push_back(bmap[k]);
+    wick_nucleus_desc d = a.desc();
+    d.n_src = (int32_t)b.re.size();
+    d.src_kind = src_kind.data();
+    d.src_re = b.re.data();
+    d.src_im = b.im.data();
+    d.scale = std::sqrt(a.scale * b.scale);
+    return build_plan(&d, out);
+}
+
+wick_status std_gevp_plan(const char *const *names, const int32_t *J, int32_t n_ops, wick_gevp_t *out)
+{
+    if (!names || !out || n_ops < 1 || n_ops > 4) return fail(WICK_EINVAL, "wick_gevp_plan_std: bad arguments");
+    std::vector<OpBuilder> obs((size_t)n_ops);
+    std::vector<wick_nucleus_desc> ds((size_t)n_ops);
+    for (int i = 0; i < n_ops; ++i) {
+        wick_status st = std_operator(names[i], J ? J[i] : 0, obs[i]);
+        if (st != WICK_OK) return st;
+    }
+    for (int i = 0; i < n_ops; ++i) ds[i] = obs[i].desc();
+    return build_gevp(ds.data(), n_ops, out);
 }
 
 }  // namespace wick

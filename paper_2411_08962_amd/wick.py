@@ -52,7 +52,8 @@ EXPORTS = ["wick_plan", "wick_plan_std", "wick_plan_info", "wick_plan_stats", "w
            "wick_contract", "wick_correlator", "wick_autotune", "wick_shutdown", "wick_last_error",
            "wick_version", "wick_profile", "wick_profile_read", "wick_point_plan", "wick_point_plan_std",
            "wick_point_info", "wick_point_correlator", "wick_point_destroy", "wick_gevp_plan", "wick_gevp_info",
-           "wick_gevp_table", "wick_gevp_kinds", "wick_gevp_contract", "wick_gevp_destroy"]
+           "wick_gevp_table", "wick_gevp_kinds", "wick_gevp_contract", "wick_gevp_destroy", "wick_gevp_plan_std",
+           "wick_plan_std_pair"]
 
 _lib = None
 
@@ -69,6 +70,7 @@ def lib():
     pp = ctypes.POINTER(ctypes.c_void_p)
     L.wick_plan.argtypes = [ctypes.POINTER(_Desc), pp]
     L.wick_plan_std.argtypes = [ctypes.c_char_p, i32, pp]
+    L.wick_plan_std_pair.argtypes = [ctypes.c_char_p, i32, ctypes.c_char_p, i32, pp]
     L.wick_plan_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)]
     L.wick_plan_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                   ctypes.POINTER(ctypes.c_double)]
@@ -91,6 +93,7 @@ def lib():
     L.wick_point_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)] + [ctypes.POINTER(i64)] * 6
     L.wick_point_correlator.argtypes = [P, P, P, st, P, i32, P, P]
     L.wick_gevp_plan.argtypes = [ctypes.POINTER(_Desc), i32, pp]
+    L.wick_gevp_plan_std.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i32), i32, pp]
     L.wick_gevp_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                                  ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.wick_gevp_table.argtypes = [P, P, P]
@@ -107,7 +110,8 @@ def lib():
                  "wick_contract",
                  "wick_correlator", "wick_autotune", "wick_shutdown", "wick_profile", "wick_profile_read",
                  "wick_point_plan", "wick_point_plan_std", "wick_point_info", "wick_point_correlator",
-                 "wick_gevp_plan", "wick_gevp_info", "wick_gevp_table", "wick_gevp_kinds", "wick_gevp_contract"):
+                 "wick_gevp_plan", "wick_gevp_info", "wick_gevp_table", "wick_gevp_kinds", "wick_gevp_contract",
+                 "wick_gevp_plan_std", "wick_plan_std_pair"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -250,6 +254,13 @@ def _desc(A, kinds, snk, src, scale=1.0, hash_seed=0, hash_trials=0, hash_sites=
     return d, keep
 
 
+def plan_std_pair(sink, source, J_sink=0, J_source=0):
+    """The correlator with built-in operator `sink` at the sink and `source` at the source."""
+    h = ctypes.c_void_p()
+    _check(lib().wick_plan_std_pair(sink.encode(), int(J_sink), source.encode(), int(J_source), ctypes.byref(h)))
+    return Plan(h.value)
+
+
 def plan(A, kinds, snk, src, scale=1.0, hash_seed=0, hash_trials=0, hash_sites=0):
     """Plan a general operator.
 
@@ -345,6 +356,16 @@ def gevp_plan(ops):
         keep.append(k)
     h = ctypes.c_void_p()
     _check(lib().wick_gevp_plan(descs, len(ops), ctypes.byref(h)))
+    return GevpPlan(h.value)
+
+
+def gevp_plan_std(names, J=None):
+    """Correlation-matrix plan of built-in operators (e.g. ["2H", "2H-", "2H0"])."""
+    n = len(names)
+    arr = (ctypes.c_char_p * n)(*[x.encode() for x in names])
+    js = (ctypes.c_int32 * n)(*([0] * n if J is None else [int(x) for x in J]))
+    h = ctypes.c_void_p()
+    _check(lib().wick_gevp_plan_std(arr, js, n, ctypes.byref(h)))
     return GevpPlan(h.value)
 
 

@@ -92,3 +92,21 @@ def test_gevp_rejects_bad_bases():
         W.gevp_plan([d] * 5)                               # more than four operators
     with pytest.raises(W.WickError):
         W.gevp_plan([])
+
+
+def test_builtin_basis_and_pair_plans_match_general_operators():
+    bas = deuteron_basis()
+    names = ["2H", "2H-", "2H0"]
+    g1 = W.gevp_plan_std(names)
+    g2 = W.gevp_plan([to_wick(o) for o in bas])
+    assert g1.info() == g2.info()
+    for a, b in zip(g1.table(), g2.table()):
+        assert np.array_equal(a, b)
+    for i in range(3):
+        for j in range(3):
+            el = gevp_element(bas, i, j)
+            e1, c1 = table_entries(el, W.plan_std_pair(names[i], names[j]))
+            e2, c2 = table_entries(el, W.plan(**to_wick(el)))
+            assert dict(zip(sorted_entries(e1), c1)) == dict(zip(sorted_entries(e2), c2))
+    with pytest.raises(W.WickError):
+        W.plan_std_pair("2H", "3He")
