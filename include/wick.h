@@ -298,6 +298,17 @@ wick_status wick_point_correlator(wick_point_t plan, const void *S_u, const void
                                   const int32_t dims[4], int32_t n_cfg, wick_stream_t stream, double *C);
 void wick_point_destroy(wick_point_t plan);
 
+/* The same point-sink correlator in the block form (Eq. 3.1): at every site
+ * the blocks of that site alone and the plane-wave plan's signed term table
+ * on them, summed over sites (C[cfg][t] = sum_x sum_n coef_n prod_a
+ * B_x[kidx_{a,n}], scale included). One fused kernel per call; the
+ * cheaper route when the table is small (A <= 3), the determinant route
+ * for helium-4. Same arguments and errors as wick_point_correlator, with a
+ * plan from wick_plan / wick_plan_std; WICK_EUNSUPPORTED above 11 block
+ * kinds. */
+wick_status wick_point_blocks_correlator(wick_plan_t plan, const void *S_u, const void *S_d, wick_dtype dtype,
+                                         const int32_t dims[4], int32_t n_cfg, wick_stream_t stream, double *C);
+
 /* Release the device workspace (blocking). */
 wick_status wick_shutdown(void);
 

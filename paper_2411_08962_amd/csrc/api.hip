@@ -1113,6 +1113,7 @@ void Probe::stop()
 
 void release_device_tables(wick_plan_s *p)
 {
+    release_plain_tables(p);
     std::lock_guard<std::mutex> lk(g_dev_mu);
     auto it = g_dev.find(p);
     if (it == g_dev.end()) return;

@@ -211,7 +211,7 @@ using namespace wick;
 wick_gevp_s::~wick_gevp_s()
 {
     release_gevp_tables(this);
-    delete carrier;
+    wick_plan_destroy(carrier);  // also drops its device tables and cached batches
 }
 
 extern "C" {

@@ -55,10 +55,13 @@ struct NucGroup {
     std::vector<int> kinds, alpha;             // block-kind indices and their sink spins
 };
 
+// Plain table and kind weights on one device, for the per-site point-sink
+// route (point.hip).
 struct DeviceTable {
     int device = -1;
     void *kidx = nullptr;   // uint16 [A][n_terms]
     void *coef = nullptr;   // double [n_terms] (real) or [n_terms][2]
+    void *kinds = nullptr;  // per-kind flavors and weight offsets, then the weights
 };
 
 struct wick_plan_impl;
@@ -76,7 +79,7 @@ struct wick_plan_s {
     bool coef_real = true;
     int64_t n_enumerated = 0, n_groups = 0;
     double bound = 0.0, scale = 1.0;
-    // device copies of the table, one per device
+    // plain device copies of the table for the per-site point-sink route, one per device
     std::mutex dev_mu;
     std::vector<wick::DeviceTable> dev;
     ~wick_plan_s();
@@ -146,6 +149,7 @@ void release_gevp_tables(wick_gevp_s *g);
 // point-sink planner (point.cpp) and device tables (point.hip)
 wick_status build_point_plan(const wick_nucleus_desc *d, wick_point_t *out);
 void release_point_tables(wick_point_s *p);
+void release_plain_tables(wick_plan_s *p);
 
 // device-table release (api.cpp)
 void release_device_tables(wick_plan_s *p);

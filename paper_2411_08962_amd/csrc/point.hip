@@ -255,6 +255,110 @@ __global__ __launch_bounds__(kPtThreads) void pt_reduce_kernel(const double2 *__
     if (threadIdx.x == 0) C[ct] = make_double2(scale * red[0].x, scale * red[0].y);
 }
 
+// ---------------------------------------------- point sinks from site blocks
+// The point-sink correlator in the block form (Eq. 3.1): at every site the
+// blocks of that site alone, then the plan's signed term table on them,
+// summed over sites. pt_site_terms_kernel: a workgroup takes S site-slices;
+// it stages their propagators, builds every kind's compact block of each
+// site in LDS (the antisymmetrised sum over the kind's weights), then every
+// thread evaluates its share of the table on all S sites. One partial per
+// site-slice; pt_reduce_kernel sums the sites of each (configuration, t).
+constexpr int kPbThreads = 512;
+
+struct PbKind {
+    int32_t f, g, n_w, off;  // slot flavors (f, g, f), weights [off, off + n_w)
+};
+
+struct PbArgs {
+    const PbKind *kinds;
+    const int8_t *wj;    // [total weights][3]
+    const double2 *ww;   // [total weights]
+    int K, A;
+    const uint16_t *kidx;
+    const double *coef;  // real [N] or complex [N][2]
+    int64_t N;
+    int64_t n_slots;
+};
+
+template <typename TIn, int S, bool REAL>
+__global__ __launch_bounds__(kPbThreads) void pt_site_terms_kernel(const TIn *__restrict__ Su,
+                                                                  const TIn *__restrict__ Sd, PbArgs a,
+                                                                  double2 *__restrict__ partial)
+{
+    extern __shared__ double2 lds[];
+    double2 *sS = lds;                // [S][2][144]
+    double2 *sB = lds + S * 288;      // [S][K * 792]
+    __shared__ double2 red[kPbThreads / 64][S];
+    const int64_t slot0 = (int64_t)blockIdx.x * S;
+    const int ns = (int)min((int64_t)S, a.n_slots - slot0);
+    for (int e = threadIdx.x; e < S * 288; e += kPbThreads) {
+        const int s = e / 288, r = e % 288, fl = r / 144, q = r % 144;
+        double2 v = make_double2(0.0, 0.0);
+        if (s < ns) {
+            const TIn *src = (fl == 0 ? Su : Sd) + (slot0 + s) * 144 + q;
+            v = make_double2((double)src->x, (double)src->y);
+        }
+        sS[e] = v;
+    }
+    __syncthreads();
+    const int KB = a.K * 792;
+    for (int e = threadIdx.x; e < S * KB; e += kPbThreads) {
+        const int s = e / KB, r = e % KB, k = r / 792, c = r % 792;
+        const int pair = c / 12, i2 = c % 12;
+        int i3 = 1;
+        while ((i3 + 1) * i3 / 2 <= pair) ++i3;
+        const int i1 = pair - i3 * (i3 - 1) / 2;
+        const PbKind kd = a.kinds[k];
+        const double2 *F = sS + s * 288 + kd.f * 144, *G = sS + s * 288 + kd.g * 144;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int w = kd.off; w < kd.off + kd.n_w; ++w) {
+            const int j1 = a.wj[3 * w], j2 = a.wj[3 * w + 1], j3 = a.wj[3 * w + 2];
+            const double2 x = cmul(F[j1 * 12 + i1], F[j3 * 12 + i3]);
+            const double2 y = cmul(F[j1 * 12 + i3], F[j3 * 12 + i1]);
+            const double2 t = cmul(a.ww[w], cmul(G[j2 * 12 + i2], make_double2(x.x - y.x, x.y - y.y)));
+            acc.x += t.x;
+            acc.y += t.y;
+        }
+        sB[e] = acc;
+    }
+    __syncthreads();
+    double2 acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = make_double2(0.0, 0.0);
+    for (int64_t n = threadIdx.x; n < a.N; n += kPbThreads) {
+        int idx[kMaxA];
+#pragma unroll
+        for (int q = 0; q < kMaxA; ++q) idx[q] = q < a.A ? a.kidx[(int64_t)q * a.N + n] : 0;
+        const double2 c = REAL ? make_double2(a.coef[n], 0.0) : make_double2(a.coef[2 * n], a.coef[2 * n + 1]);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const double2 *B = sB + s * KB;
+            double2 p = B[idx[0]];
+#pragma unroll
+            for (int q = 1; q < kMaxA; ++q)
+                if (q < a.A) p = cmul(p, B[idx[q]]);
+            const double2 t = REAL ? make_double2(c.x * p.x, c.x * p.y) : cmul(c, p);
+            acc[s].x += t.x;
+            acc[s].y += t.y;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        double2 v = acc[s];
+        for (int o = 32; o > 0; o >>= 1) {
+            v.x += __shfl_down(v.x, o, 64);
+            v.y += __shfl_down(v.y, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][s] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < ns) {
+        double2 v = red[0][threadIdx.x];
+        for (int w = 1; w < kPbThreads / 64; ++w) { v.x += red[w][threadIdx.x].x; v.y += red[w][threadIdx.x].y; }
+        partial[slot0 + threadIdx.x] = v;
+    }
+}
+
 // ------------------------------------------------------------ host side
 wick_status pt_hip_fail(hipError_t e, const char *what)
 {
@@ -453,6 +557,145 @@ wick_status launch_point(wick_point_s *p, PtDev *d, const TIn *Su, const TIn *Sd
     return e == hipSuccess ? WICK_OK : pt_hip_fail(e, "pt_reduce_kernel");
 }
 
+// The plan's plain table and kind weights on the current device (cached in
+// the plan, released with it).
+wick_status plain_tables(wick_plan_s *p, DeviceTable *out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return pt_hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(p->dev_mu);
+    for (auto &d : p->dev)
+        if (d.device == dev) { *out = d; return WICK_OK; }
+    DeviceTable d;
+    d.device = dev;
+    const int K = (int)p->kinds.size();
+    std::vector<PbKind> kinds(K);
+    std::vector<int8_t> wj;
+    std::vector<double2> ww;
+    for (int k = 0; k < K; ++k) {
+        const KindDef &kd = p->kinds[k];
+        kinds[k] = PbKind{kd.flav[0], kd.flav[1], (int32_t)kd.w.size(), (int32_t)ww.size()};
+        for (size_t n = 0; n < kd.w.size(); ++n) {
+            for (int q = 0; q < 3; ++q) wj.push_back(kd.j[n][q]);
+            ww.push_back(make_double2((double)kd.w[n].re, (double)kd.w[n].im));
+        }
+    }
+    // one buffer: kinds, then weights (16-byte aligned), then weight indices
+    const size_t kb = ((K * sizeof(PbKind)) + 15) / 16 * 16, wb = ww.size() * sizeof(double2);
+    std::vector<char> blob(kb + wb + wj.size() + 16, 0);
+    std::memcpy(blob.data(), kinds.data(), K * sizeof(PbKind));
+    std::memcpy(blob.data() + kb, ww.data(), wb);
+    std::memcpy(blob.data() + kb + wb, wj.data(), wj.size());
+    const size_t N = (size_t)p->n_terms;
+    std::vector<double> coef(p->coef_real ? N : 2 * N);
+    for (size_t n = 0; n < N; ++n) {
+        if (p->coef_real) coef[n] = p->coef_re[n];
+        else { coef[2 * n] = p->coef_re[n]; coef[2 * n + 1] = p->coef_im[n]; }
+    }
+    const size_t ib = std::max<size_t>(1, p->kidx.size()) * sizeof(uint16_t), cb = std::max<size_t>(1, coef.size()) * 8;
+    if ((e = hipMalloc(&d.kinds, blob.size())) != hipSuccess || (e = hipMalloc(&d.kidx, ib)) != hipSuccess ||
+        (e = hipMalloc(&d.coef, cb)) != hipSuccess) {
+        (void)hipFree(d.kinds);
+        (void)hipFree(d.kidx);
+        return fail(WICK_ENOMEM, std::string("wick_point_blocks_correlator: hipMalloc: ") + hipGetErrorString(e));
+    }
+    if ((e = hipMemcpy(d.kinds, blob.data(), blob.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (!p->kidx.empty() && (e = hipMemcpy(d.kidx, p->kidx.data(), p->kidx.size() * 2, hipMemcpyHostToDevice)) != hipSuccess) ||
+        (!coef.empty() && (e = hipMemcpy(d.coef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)) {
+        (void)hipFree(d.kinds);
+        (void)hipFree(d.kidx);
+        (void)hipFree(d.coef);
+        return pt_hip_fail(e, "wick_point_blocks_correlator: hipMemcpy");
+    }
+    p->dev.push_back(d);
+    *out = d;
+    return WICK_OK;
+}
+
+template <typename TIn, int S>
+void launch_site_terms(bool real, dim3 grid, size_t shmem, hipStream_t s, const TIn *Su, const TIn *Sd,
+                       const PbArgs &a, double2 *partial)
+{
+    if (real) pt_site_terms_kernel<TIn, S, true><<<grid, kPbThreads, shmem, s>>>(Su, Sd, a, partial);
+    else pt_site_terms_kernel<TIn, S, false><<<grid, kPbThreads, shmem, s>>>(Su, Sd, a, partial);
+}
+
+template <typename TIn>
+wick_status set_site_terms_lds(int S, size_t shmem)
+{
+    hipError_t e = hipSuccess;
+    const int v = (int)shmem;
+    switch (S) {
+    case 1:
+        if ((e = hipFuncSetAttribute((const void *)pt_site_terms_kernel<TIn, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) != hipSuccess ||
+            (e = hipFuncSetAttribute((const void *)pt_site_terms_kernel<TIn, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) != hipSuccess)
+            return pt_hip_fail(e, "hipFuncSetAttribute");
+        break;
+    case 2:
+        if ((e = hipFuncSetAttribute((const void *)pt_site_terms_kernel<TIn, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) != hipSuccess ||
+            (e = hipFuncSetAttribute((const void *)pt_site_terms_kernel<TIn, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) != hipSuccess)
+            return pt_hip_fail(e, "hipFuncSetAttribute");
+        break;
+    default:
+        if ((e = hipFuncSetAttribute((const void *)pt_site_terms_kernel<TIn, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) != hipSuccess ||
+            (e = hipFuncSetAttribute((const void *)pt_site_terms_kernel<TIn, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) != hipSuccess)
+            return pt_hip_fail(e, "hipFuncSetAttribute");
+        break;
+    }
+    return WICK_OK;
+}
+
+template <typename TIn>
+wick_status launch_point_blocks(wick_plan_s *p, const DeviceTable *d, const TIn *Su, const TIn *Sd, int64_t V, int64_t n_ct,
+                                hipStream_t s, double2 *C)
+{
+    const int64_t slots = V * n_ct;
+    if (p->n_terms == 0) {
+        hipError_t e = launch_zero((double *)C, 2 * n_ct, s);
+        return e == hipSuccess ? WICK_OK : pt_hip_fail(e, "zero_kernel");
+    }
+    const int K = (int)p->kinds.size();
+    const size_t per_site = (size_t)(288 + K * 792) * sizeof(double2);
+    constexpr size_t kLds = 152 * 1024;
+    const int S = per_site * 4 <= kLds ? 4 : per_site * 2 <= kLds ? 2 : 1;
+    const size_t shmem = per_site * S;
+    if (shmem > kLds) return fail(WICK_EUNSUPPORTED, "wick_point_blocks_correlator: too many block kinds for LDS");
+    void *ws = nullptr;
+    wick_status st = workspace(s, (size_t)slots * sizeof(double2), &ws);
+    if (st != WICK_OK) return st;
+    if (shmem > 64 * 1024 && (st = set_site_terms_lds<TIn>(S, shmem)) != WICK_OK) return st;
+    PbArgs a{};
+    const size_t kb = ((K * sizeof(PbKind)) + 15) / 16 * 16;
+    size_t nw = 0;
+    for (auto &kd : p->kinds) nw += kd.w.size();
+    a.kinds = (const PbKind *)d->kinds;
+    a.ww = (const double2 *)((const char *)d->kinds + kb);
+    a.wj = (const int8_t *)((const char *)d->kinds + kb + nw * sizeof(double2));
+    a.K = K;
+    a.A = p->A;
+    a.kidx = (const uint16_t *)d->kidx;
+    a.coef = (const double *)d->coef;
+    a.N = p->n_terms;
+    a.n_slots = slots;
+    double2 *partial = (double2 *)ws;
+    const int64_t nwg = (slots + S - 1) / S;
+    if (nwg > (1LL << 31) - 1) return fail(WICK_ETOOBIG, "wick_point_blocks_correlator: lattice too large");
+    const dim3 grid((unsigned)nwg);
+    Probe pr("point_site_terms", s);
+    if (S == 4) launch_site_terms<TIn, 4>(p->coef_real, grid, shmem, s, Su, Sd, a, partial);
+    else if (S == 2) launch_site_terms<TIn, 2>(p->coef_real, grid, shmem, s, Su, Sd, a, partial);
+    else launch_site_terms<TIn, 1>(p->coef_real, grid, shmem, s, Su, Sd, a, partial);
+    pr.stop();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return pt_hip_fail(e, "pt_site_terms_kernel");
+    Probe pc("point_reduce", s);
+    pt_reduce_kernel<<<dim3((unsigned)n_ct), dim3(kPtThreads), 0, s>>>(partial, V, 1.0, C);
+    pc.stop();
+    e = hipGetLastError();
+    return e == hipSuccess ? WICK_OK : pt_hip_fail(e, "pt_reduce_kernel");
+}
+
 }  // namespace
 
 void release_point_tables(wick_point_s *p)
@@ -469,9 +712,52 @@ void release_point_tables(wick_point_s *p)
     (void)hipSetDevice(cur);
 }
 
+void release_plain_tables(wick_plan_s *p)
+{
+    std::lock_guard<std::mutex> lk(p->dev_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &d : p->dev) {
+        (void)hipSetDevice(d.device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(d.kinds);
+        (void)hipFree(d.kidx);
+        (void)hipFree(d.coef);
+    }
+    p->dev.clear();
+    (void)hipSetDevice(cur);
+}
+
 }  // namespace wick
 
 using namespace wick;
+
+extern "C" wick_status wick_point_blocks_correlator(wick_plan_t p, const void *S_u, const void *S_d, wick_dtype dtype,
+                                                    const int32_t dims[4], int32_t n_cfg, wick_stream_t stream,
+                                                    double *C)
+{
+    try {
+        if (!p || !S_u || !S_d || !C) return fail(WICK_EINVAL, "wick_point_blocks_correlator: null pointer");
+        if (((uintptr_t)S_u | (uintptr_t)S_d | (uintptr_t)C) & 15)
+            return fail(WICK_EINVAL, "wick_point_blocks_correlator: propagators and C must be 16-byte aligned");
+        if (dtype != WICK_C128 && dtype != WICK_C64) return fail(WICK_EINVAL, "wick_point_blocks_correlator: bad dtype");
+        const int64_t V = check_point_dims(dims, n_cfg);
+        if (V == -1) return fail(WICK_EINVAL, "wick_point_blocks_correlator: bad dims or n_cfg");
+        if (V < 0) return fail(WICK_ETOOBIG, "wick_point_blocks_correlator: lattice too large");
+        const int64_t n_ct = (int64_t)n_cfg * dims[3];
+        DeviceTable d;
+        wick_status st = plain_tables(p, &d);
+        if (st != WICK_OK) return st;
+        hipStream_t s = (hipStream_t)stream;
+        if (dtype == WICK_C128)
+            return launch_point_blocks(p, &d, (const double2 *)S_u, (const double2 *)S_d, V, n_ct, s, (double2 *)C);
+        return launch_point_blocks(p, &d, (const float2 *)S_u, (const float2 *)S_d, V, n_ct, s, (double2 *)C);
+    } catch (const std::bad_alloc &) {
+        return fail(WICK_ENOMEM, "wick_point_blocks_correlator: out of host memory");
+    } catch (...) {
+        return fail(WICK_EINVAL, "wick_point_blocks_correlator: internal error");
+    }
+}
 
 extern "C" wick_status wick_point_correlator(wick_point_t p, const void *S_u, const void *S_d, wick_dtype dtype,
                                              const int32_t dims[4], int32_t n_cfg, wick_stream_t stream, double *C)

@@ -53,7 +53,7 @@ EXPORTS = ["wick_plan", "wick_plan_std", "wick_plan_info", "wick_plan_stats", "w
            "wick_version", "wick_profile", "wick_profile_read", "wick_point_plan", "wick_point_plan_std",
            "wick_point_info", "wick_point_correlator", "wick_point_destroy", "wick_gevp_plan", "wick_gevp_info",
            "wick_gevp_table", "wick_gevp_kinds", "wick_gevp_contract", "wick_gevp_destroy", "wick_gevp_plan_std",
-           "wick_plan_std_pair"]
+           "wick_plan_std_pair", "wick_point_blocks_correlator"]
 
 _lib = None
 
@@ -92,6 +92,7 @@ def lib():
     L.wick_point_plan_std.argtypes = [ctypes.c_char_p, i32, pp]
     L.wick_point_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)] + [ctypes.POINTER(i64)] * 6
     L.wick_point_correlator.argtypes = [P, P, P, st, P, i32, P, P]
+    L.wick_point_blocks_correlator.argtypes = [P, P, P, st, P, i32, P, P]
     L.wick_gevp_plan.argtypes = [ctypes.POINTER(_Desc), i32, pp]
     L.wick_gevp_plan_std.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i32), i32, pp]
     L.wick_gevp_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -111,7 +112,7 @@ def lib():
                  "wick_correlator", "wick_autotune", "wick_shutdown", "wick_profile", "wick_profile_read",
                  "wick_point_plan", "wick_point_plan_std", "wick_point_info", "wick_point_correlator",
                  "wick_gevp_plan", "wick_gevp_info", "wick_gevp_table", "wick_gevp_kinds", "wick_gevp_contract",
-                 "wick_gevp_plan_std", "wick_plan_std_pair"):
+                 "wick_gevp_plan_std", "wick_plan_std_pair", "wick_point_blocks_correlator"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -491,6 +492,19 @@ def point_correlator(p: PointPlan, S_u, S_d, out=None):
     _check_out(out, (n_cfg, T, 2), S_u.device)
     _check(lib().wick_point_correlator(p.handle, ctypes.c_void_p(S_u.data_ptr()), ctypes.c_void_p(S_d.data_ptr()),
                                        dtype, dims, n_cfg, _stream(), ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def point_blocks_correlator(p: Plan, S_u, S_d, out=None):
+    """Point-sink C [n_cfg, T, 2] in the block form: per-site blocks and the plan's term table."""
+    torch = _torch()
+    n_cfg, T, dims, dtype = _prop_args(S_u, S_d)
+    if out is None:
+        out = torch.empty((n_cfg, T, 2), dtype=torch.float64, device=S_u.device)
+    _check_out(out, (n_cfg, T, 2), S_u.device)
+    _check(lib().wick_point_blocks_correlator(p.handle, ctypes.c_void_p(S_u.data_ptr()),
+                                              ctypes.c_void_p(S_d.data_ptr()), dtype, dims, n_cfg, _stream(),
+                                              ctypes.c_void_p(out.data_ptr())))
     return out
 
 

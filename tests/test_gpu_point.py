@@ -155,3 +155,50 @@ def test_point_argument_errors():
     assert L.wick_point_correlator(pp.handle, P(du.data_ptr()), P(dd.data_ptr()), 0, bad, 1, s, P(C.data_ptr())) == w.EINVAL
     assert L.wick_point_correlator(pp.handle, P(du.data_ptr()), P(dd.data_ptr()), 7, dims, 1, s, P(C.data_ptr())) == w.EINVAL
     torch.cuda.synchronize()
+
+
+# ------------------------------------------------ block form (Eq. 3.1)
+BLOCK_CASES = [
+    ("1H", lambda: ops.proton(1), (3, 2, 2, 3)),
+    ("2H", ops.deuteron, (2, 2, 2, 2)),
+    ("3He", ops.helium3, (2, 2, 1, 2)),
+    ("4He", ops.helium4, (2, 1, 1, 1)),
+]
+
+
+@pytest.mark.parametrize("name,make,dims", BLOCK_CASES, ids=[c[0] for c in BLOCK_CASES])
+def test_point_block_form_matches_oracle(name, make, dims):
+    w = W()
+    op = make()
+    pl = w.plan_std(name, 1) if name == "1H" else w.plan_std(name)
+    hu, hd, du, dd = props(971, 1, dims)
+    C = w.point_blocks_correlator(pl, du, dd).cpu().numpy()
+    check(op, None, hu, hd, C)
+
+
+def test_point_block_form_equals_determinants_on_a_lattice():
+    # the two routes to the same point-sink correlator, on 4^3 x 3 (2H) and 3x3x2 x 2 (3He)
+    w = W()
+    for name, op, dims in (("2H", ops.deuteron(), (4, 4, 4, 3)), ("3He", ops.helium3(), (3, 3, 2, 2))):
+        hu, hd, du, dd = props(972, 1, dims)
+        Cb = w.point_blocks_correlator(w.plan_std(name), du, dd).cpu().numpy()[0]
+        Cd = w.point_correlator(w.point_plan_std(name), du, dd).cpu().numpy()[0]
+        mag = oracle.point_det_magnitude(op, hu[0], hd[0])
+        d = np.abs((Cb[:, 0] - Cd[:, 0]) + 1j * (Cb[:, 1] - Cd[:, 1]))
+        assert np.all(d <= 10 * TOL * mag), (name, d, mag)
+
+
+def test_point_block_form_general_plan_complex64_and_empty():
+    w = W()
+    op = ops.sparsify(ops.helium3(), 6, np.random.default_rng(4))
+    pl = w.plan(**to_wick(op))
+    hu, hd, du, dd = props(973, 1, (2, 2, 1, 2), np.complex64)
+    C = w.point_blocks_correlator(pl, du, dd).cpu().numpy()
+    check(op, None, hu, hd, C)
+    # a plan whose table is empty gives zeros
+    kinds = [((0, 1, 0), [(0, 1, 0, 1, 0), (3, 2, 3, 1, 0)])]
+    pe = w.plan(A=1, kinds=kinds, snk=[((0,), (1, 0))], src=[((0,), (1, 0))])
+    assert pe.n_terms == 0
+    Cz = _torch().full((1, 2, 2), 5.0, dtype=_torch().float64, device="cuda")
+    w.point_blocks_correlator(pe, du, dd, out=Cz)
+    assert np.all(Cz.cpu().numpy() == 0)
