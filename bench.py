@@ -467,6 +467,31 @@ def point_bench(args):
         "paper_s_per_time_slice_24cubed": PAPER_POINT_24.get(nucleus),
         "kernel_ms": ms,
     }
+    if nucleus in ("2H", "3He"):
+        # the same correlator in the block form (per-site blocks and the plane-wave table)
+        pl = W.plan_std(nucleus)
+        Cb = torch.empty_like(C)
+        for _ in range(max(args.warmup, 1)):
+            W.point_blocks_correlator(pl, du, dd, out=Cb)
+        torch.cuda.synchronize()
+        W.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            W.point_blocks_correlator(pl, du, dd, out=Cb)
+        torch.cuda.synchronize()
+        dtb = (time.perf_counter() - t0) / args.steps
+        W.profile(False)
+        nb, msb = W.profile_read("point_site_terms")
+        A, K, N = pl.info()
+        nw = sum(len(pl.kind(k)[1]) for k in range(K))
+        # per site: 28 flops per (block entry, weight) of the block build, 6A + 2 per term
+        f_site = 792 * nw * 28 + N * (6 * A + 2)
+        tf = f_site * slots / (msb / max(nb, 1) * 1e-3) / 1e12
+        cb, cd = Cb.cpu().numpy()[0], C.cpu().numpy()[0]
+        dev = np.max(np.abs((cb[:, 0] - cd[:, 0]) + 1j * (cb[:, 1] - cd[:, 1])) / np.abs(cd[:, 0] + 1j * cd[:, 1]))
+        out["block_form"] = {"ms_per_step": 1e3 * dtb, "s_per_time_slice": dtb / T, "speedup_vs_determinants": step_s / dtb,
+                             "table_terms": N, "kernel": "pt_site_terms_kernel", "achieved_TFLOPs": tf, "frac_fp64_alu": tf / 78.6,
+                             "max_rel_diff_vs_determinants": float(dev)}
     if not args.no_cpu_baseline:
         note("cpu baseline (oracle point route)")
         import oracle
