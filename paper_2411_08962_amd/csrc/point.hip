@@ -12,10 +12,14 @@
 // sum_k binom(12,k) k complex multiply-adds per row set (6744 for n = 5),
 // a few per determinant, and is division-free.
 //
+// Row sets are sorted, so a workgroup's consecutive row sets often share
+// their first n-1 rows: levels 1..n-1 are then kept, and level n is formed
+// only for the column sets the source uses.
+//
 // Kernels (one site-slice per "slot"):
-//   pt_minors_kernel: the d minors of every sink row set, kept for the
-//     source column sets only, to a workspace [slot][row set][column set].
-//   pt_pairs_kernel: the u minors of a chunk of sink row sets in LDS, then
+//   pt_minors_kernel: the d determinants of every sink row set at the source
+//     column sets, to a workspace [slot][row set][column set].
+//   pt_pairs_kernel: the u determinants of a chunk of sink row sets in LDS, then
 //     for every sink group g of those row sets the sum over source groups h
 //     of W'_h det_u[U_g; U'_h] det_d[D_g; D'_h], times W_g (the Theta-weighted
 //     double sum of Eq. A1), into one partial per (slot, chunk).
@@ -39,7 +43,6 @@ wick_status workspace(hipStream_t s, size_t bytes, void **out);
 namespace {
 
 constexpr int kPtThreads = 256;
-constexpr int kPtMaxMinors = 924;   // binom(12, 6)
 constexpr int kPtSubsets = 2509;    // sum_{k=1..6} binom(12, k)
 constexpr int kPtRowsPerWG = 8;     // sink row sets per workgroup
 
@@ -70,11 +73,11 @@ struct PtDev {
     int8_t *rows_u = nullptr, *rows_d = nullptr;   // [n][8]
     int32_t *u_beg = nullptr, *g_d = nullptr;
     double2 *g_w = nullptr;
-    uint16_t *h_ru = nullptr;                      // source groups sorted by d column: u column rank
+    uint16_t *h_ru = nullptr;                      // source groups sorted by d column: compact u column
     double2 *h_w = nullptr;                        // and weight
     int32_t *cd_beg = nullptr;                     // [n_cd + 1] source groups of each d column
-    uint16_t *d_cols = nullptr;                    // compact d column index -> rank
-    int n_cd = 0;
+    uint16_t *d_cols = nullptr, *u_cols = nullptr; // compact column index -> colex rank
+    int n_cd = 0, n_cu = 0;
 };
 
 struct PtArgs {
@@ -82,10 +85,10 @@ struct PtArgs {
     const int8_t *rows_u, *rows_d;
     const int32_t *u_beg, *g_d;
     const double2 *g_w;
-    const uint16_t *h_ru, *d_cols;
+    const uint16_t *h_ru, *d_cols, *u_cols;  // h_ru: compact u column of each source group
     const int32_t *cd_beg;
     const double2 *h_w;
-    int n_u, n_d, n_rows_u, n_rows_d, n_h, n_cd;
+    int n_u, n_d, n_rows_u, n_rows_d, n_h, n_cd, n_cu;
     int n_uchunks, n_dchunks;
     int64_t slot0;       // first site-slice of this launch
     int n_slots;         // site-slices in this launch
@@ -111,17 +114,18 @@ __device__ __forceinline__ void stage_site(const TIn *__restrict__ S, int64_t sl
     for (int e = threadIdx.x; e < 144; e += kPtThreads) sS[e] = make_double2((double)p[e].x, (double)p[e].y);
 }
 
-// All minors of rows R[0..N) of the staged 12x12 matrix, level by level;
-// returns the LDS buffer that holds level N (binom(12, N) entries by colex rank).
-template <int N>
-__device__ double2 *minors(const PtSubset *__restrict__ T, const double2 *sS, const int8_t *R, double2 *buf0,
-                           double2 *buf1)
+// Levels 1..M of the minors of rows R[0..M) of the staged 12x12 matrix, in
+// ping-pong LDS buffers of binom(12, M) entries; returns the buffer holding
+// level M (entry = colex rank of the column subset).
+template <int M>
+__device__ const double2 *levels(const PtSubset *__restrict__ T, const double2 *sS, const int8_t *R, double2 *buf0,
+                                 double2 *buf1)
 {
     if (threadIdx.x == 0) buf0[0] = make_double2(1.0, 0.0);
     __syncthreads();
     double2 *prev = buf0, *cur = buf1;
 #pragma unroll
-    for (int k = 1; k <= N; ++k) {
+    for (int k = 1; k <= M; ++k) {
         const double2 *srow = sS + 12 * R[k - 1];
         const PtSubset *lev = T + level_off(k);
         for (int r = threadIdx.x; r < binom12c(k); r += kPtThreads) {
@@ -143,11 +147,43 @@ __device__ double2 *minors(const PtSubset *__restrict__ T, const double2 *sS, co
     return prev;
 }
 
+// One minor of the last level N: the column subset of colex rank `rank`,
+// expanded along row `row` over the level N-1 minors in Lp.
+template <int N>
+__device__ __forceinline__ double2 last_minor(const PtSubset *__restrict__ T, const double2 *srow, const double2 *Lp,
+                                              int rank)
+{
+    if (N == 0) return make_double2(1.0, 0.0);
+    const PtSubset e = T[level_off(N) + rank];
+    double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const double2 t = cmul(srow[(e.elems >> (4 * j)) & 15], Lp[e.sub[j]]);
+        if ((N - 1 + j) & 1) { s.x -= t.x; s.y -= t.y; }
+        else { s.x += t.x; s.y += t.y; }
+    }
+    return s;
+}
+
+// Whether row set r shares its first N-1 rows with row set r-1 (rows sorted
+// lexicographically, so such row sets are adjacent): then the levels below N
+// are the same and are kept.
+template <int N>
+__device__ __forceinline__ bool same_prefix(const int8_t *rows, int r, int r0)
+{
+    if (r == r0) return false;
+    bool same = true;
+#pragma unroll
+    for (int q = 0; q + 1 < N; ++q) same = same && rows[8 * r + q] == rows[8 * (r - 1) + q];
+    return same;
+}
+
 template <typename TIn, int ND>
 __global__ __launch_bounds__(kPtThreads) void pt_minors_kernel(const TIn *__restrict__ Sd, PtArgs a)
 {
+    constexpr int LB = binom12c(ND > 0 ? ND - 1 : 0);
     __shared__ double2 sS[144];
-    __shared__ double2 buf[2][kPtMaxMinors];
+    __shared__ double2 buf[2][LB];
     const int total = a.n_slots * a.n_dchunks;
     const int id = xcd_id(gridDim.x);
     if (id >= total) return;
@@ -155,11 +191,14 @@ __global__ __launch_bounds__(kPtThreads) void pt_minors_kernel(const TIn *__rest
     stage_site(Sd, a.slot0 + slot, sS);
     __syncthreads();
     const int r0 = chunk * kPtRowsPerWG, r1 = min(a.n_rows_d, r0 + kPtRowsPerWG);
+    const double2 *Lp = buf[0];
     for (int r = r0; r < r1; ++r) {
-        const double2 *L = minors<ND>(a.sub, sS, a.rows_d + 8 * r, buf[0], buf[1]);
+        const int8_t *R = a.rows_d + 8 * r;
+        if (!same_prefix<ND>(a.rows_d, r, r0)) Lp = levels<(ND > 0 ? ND - 1 : 0)>(a.sub, sS, R, buf[0], buf[1]);
+        const double2 *srow = sS + 12 * (ND > 0 ? R[ND - 1] : 0);
         double2 *out = a.dd + ((int64_t)slot * a.n_rows_d + r) * a.n_cd;
-        for (int c = threadIdx.x; c < a.n_cd; c += kPtThreads) out[c] = L[a.d_cols[c]];
-        __syncthreads();
+        for (int c = threadIdx.x; c < a.n_cd; c += kPtThreads) out[c] = last_minor<ND>(a.sub, srow, Lp, a.d_cols[c]);
+        __syncthreads();  // Lp is read until here; the next row set may rebuild it
     }
 }
 
@@ -167,16 +206,20 @@ __global__ __launch_bounds__(kPtThreads) void pt_minors_kernel(const TIn *__rest
 // source d column set c: for a sink u row set U,
 //   A_U[c] = sum over source groups h with D'_h = c of W'_h det_u[U; U'_h]
 // (source groups are sorted by c, so each c owns a contiguous range), and
-// every sink group g of U adds W_g sum_c A_U[c] det_d[D_g; c]. Thread t owns
-// the columns c = t + 256 i (i < CS): it builds their A_U[c] from the u minors
-// in LDS, then reads the d determinants of each sink group at its own columns
+// every sink group g of U adds W_g sum_c A_U[c] det_d[D_g; c]. The u
+// determinants of U are formed for the source u column sets only (compact
+// index), from level N-1 kept across row sets with equal leading rows.
+// Thread t owns the d columns c = t + 256 i (i < CS): it builds their A_U[c],
+// then reads the d determinants of each sink group at its own columns
 // (contiguous across the wave).
 template <typename TIn, int NU, int CS>
 __global__ __launch_bounds__(kPtThreads) void pt_pairs_kernel(const TIn *__restrict__ Su, PtArgs a)
 {
+    constexpr int LB = binom12c(NU > 0 ? NU - 1 : 0);
     __shared__ double2 sS[144];
-    __shared__ double2 buf[2][kPtMaxMinors];
+    __shared__ double2 buf[2][LB];
     __shared__ double2 red[kPtThreads / 64];
+    extern __shared__ double2 du[];  // [n_cu] u determinants of the current row set
     const int total = a.n_slots * a.n_uchunks;
     const int id = xcd_id(gridDim.x);
     if (id >= total) return;
@@ -193,14 +236,19 @@ __global__ __launch_bounds__(kPtThreads) void pt_pairs_kernel(const TIn *__restr
     double2 tot = make_double2(0.0, 0.0);
     const int r0 = chunk * kPtRowsPerWG, r1 = min(a.n_rows_u, r0 + kPtRowsPerWG);
     const double2 *ddslot = a.dd + (int64_t)slot * a.n_rows_d * a.n_cd;
+    const double2 *Lp = buf[0];
     for (int r = r0; r < r1; ++r) {
-        const double2 *L = minors<NU>(a.sub, sS, a.rows_u + 8 * r, buf[0], buf[1]);
+        const int8_t *R = a.rows_u + 8 * r;
+        if (!same_prefix<NU>(a.rows_u, r, r0)) Lp = levels<(NU > 0 ? NU - 1 : 0)>(a.sub, sS, R, buf[0], buf[1]);
+        const double2 *srow = sS + 12 * (NU > 0 ? R[NU - 1] : 0);
+        for (int c = threadIdx.x; c < a.n_cu; c += kPtThreads) du[c] = last_minor<NU>(a.sub, srow, Lp, a.u_cols[c]);
+        __syncthreads();
         double2 av[CS];
 #pragma unroll
         for (int i = 0; i < CS; ++i) {
             double2 acc = make_double2(0.0, 0.0);
             for (int h = hb[i]; h < he[i]; ++h) {
-                const double2 t = cmul(a.h_w[h], L[a.h_ru[h]]);
+                const double2 t = cmul(a.h_w[h], du[a.h_ru[h]]);
                 acc.x += t.x;
                 acc.y += t.y;
             }
@@ -415,6 +463,7 @@ void free_dev(PtDev *d)
     (void)hipFree(d->cd_beg);
     (void)hipFree(d->h_w);
     (void)hipFree(d->d_cols);
+    (void)hipFree(d->u_cols);
     delete d;
 }
 
@@ -441,6 +490,11 @@ wick_status device_tables(wick_point_s *p, PtDev **out)
     std::vector<uint16_t> dcols;
     for (auto &c : cols) { c.second = (int)dcols.size(); dcols.push_back((uint16_t)c.first); }
     d->n_cd = (int)dcols.size();
+    std::map<int, int> ucols;
+    for (uint16_t r : p->h_ru) ucols.emplace(r, 0);
+    std::vector<uint16_t> ucl;
+    for (auto &c : ucols) { c.second = (int)ucl.size(); ucl.push_back((uint16_t)c.first); }
+    d->n_cu = (int)ucl.size();
     // source groups ordered by (d column, u column), with the range of each d column
     const size_t H = p->h_ru.size();
     std::vector<size_t> ord(H);
@@ -453,7 +507,7 @@ wick_status device_tables(wick_point_s *p, PtDev **out)
     std::vector<int32_t> cdb(d->n_cd + 1, 0);
     for (size_t i = 0; i < H; ++i) {
         const size_t h = ord[i];
-        hru[i] = p->h_ru[h];
+        hru[i] = (uint16_t)ucols[p->h_ru[h]];
         hw[i] = make_double2(p->h_w[2 * h], p->h_w[2 * h + 1]);
         cdb[cols[p->h_rd[h]] + 1]++;
     }
@@ -463,7 +517,8 @@ wick_status device_tables(wick_point_s *p, PtDev **out)
         (st = upload(rd, &d->rows_d)) != WICK_OK || (st = upload(p->u_beg, &d->u_beg)) != WICK_OK ||
         (st = upload(p->g_d, &d->g_d)) != WICK_OK || (st = upload(gw, &d->g_w)) != WICK_OK ||
         (st = upload(hru, &d->h_ru)) != WICK_OK || (st = upload(cdb, &d->cd_beg)) != WICK_OK ||
-        (st = upload(hw, &d->h_w)) != WICK_OK || (st = upload(dcols, &d->d_cols)) != WICK_OK) {
+        (st = upload(hw, &d->h_w)) != WICK_OK || (st = upload(dcols, &d->d_cols)) != WICK_OK ||
+        (st = upload(ucl, &d->u_cols)) != WICK_OK) {
         free_dev(d);
         return st;
     }
@@ -502,6 +557,7 @@ wick_status launch_point(wick_point_s *p, PtDev *d, const TIn *Su, const TIn *Sd
     a.h_ru = d->h_ru;
     a.cd_beg = d->cd_beg;
     a.d_cols = d->d_cols;
+    a.u_cols = d->u_cols;
     a.h_w = d->h_w;
     a.n_u = p->n_u;
     a.n_d = p->n_d;
@@ -509,6 +565,7 @@ wick_status launch_point(wick_point_s *p, PtDev *d, const TIn *Su, const TIn *Sd
     a.n_rows_d = (int)p->rows_d.size();
     a.n_h = (int)p->h_ru.size();
     a.n_cd = d->n_cd;
+    a.n_cu = d->n_cu;
     a.n_uchunks = (a.n_rows_u + kPtRowsPerWG - 1) / kPtRowsPerWG;
     a.n_dchunks = (a.n_rows_d + kPtRowsPerWG - 1) / kPtRowsPerWG;
     const size_t per_slot_dd = (size_t)a.n_rows_d * a.n_cd * sizeof(double2);
@@ -537,12 +594,13 @@ wick_status launch_point(wick_point_s *p, PtDev *d, const TIn *Su, const TIn *Sd
         pa.stop();
         Probe pb("point_pairs", s);
         const int cs = (a.n_cd + kPtThreads - 1) / kPtThreads;  // 1..4 (n_cd <= 924)
+        const size_t shu = (size_t)std::max(1, a.n_cu) * sizeof(double2);  // <= 924 entries: 14.8 KB
         switch (a.n_u * 4 + cs - 1) {
 #define PT_PAIRS(n)                                                                \
-    case 4 * n + 0: pt_pairs_kernel<TIn, n, 1><<<gu, blk, 0, s>>>(Su, a); break;  \
-    case 4 * n + 1: pt_pairs_kernel<TIn, n, 2><<<gu, blk, 0, s>>>(Su, a); break;  \
-    case 4 * n + 2: pt_pairs_kernel<TIn, n, 3><<<gu, blk, 0, s>>>(Su, a); break;  \
-    case 4 * n + 3: pt_pairs_kernel<TIn, n, 4><<<gu, blk, 0, s>>>(Su, a); break;
+    case 4 * n + 0: pt_pairs_kernel<TIn, n, 1><<<gu, blk, shu, s>>>(Su, a); break;  \
+    case 4 * n + 1: pt_pairs_kernel<TIn, n, 2><<<gu, blk, shu, s>>>(Su, a); break;  \
+    case 4 * n + 2: pt_pairs_kernel<TIn, n, 3><<<gu, blk, shu, s>>>(Su, a); break;  \
+    case 4 * n + 3: pt_pairs_kernel<TIn, n, 4><<<gu, blk, shu, s>>>(Su, a); break;
             PT_PAIRS(0) PT_PAIRS(1) PT_PAIRS(2) PT_PAIRS(3) PT_PAIRS(4) PT_PAIRS(5) PT_PAIRS(6)
 #undef PT_PAIRS
         }
