@@ -224,3 +224,14 @@ def test_truncate_rejects_bad_arguments():
     assert L.wick_plan_truncate(pl.handle, None, 1, 0.5, ctypes.byref(h), None) == W.EINVAL
     assert L.wick_plan_truncate(None, B.ctypes.data_as(ctypes.c_void_p), 1, 0.5, ctypes.byref(h), None) == W.EINVAL
     assert L.wick_plan_truncate(pl.handle, B.ctypes.data_as(ctypes.c_void_p), 1, 0.5, None, None) == W.EINVAL
+
+
+def test_truncate_complex_coefficient_plan():
+    # complex couplings: the kept coefficients stay complex and the selection matches the oracle's
+    op = ops.deuteron()
+    snk = [(k, (c[0] - 2 * c[1], 2 * c[0] + c[1])) for k, c in op.snk]
+    src = [(k, (2 * c[0] + c[1], -c[0] + 2 * c[1])) for k, c in op.src]
+    opc = ops.Operator(op.A, op.kinds, snk, src, op.scale, "2H-complex")
+    pl = W.plan(**to_wick(opc))
+    tp, kept, keys, cm = check_truncation(opc, pl, props(2, 917, t=(0, 1)), 0.25)
+    assert np.any(tp.table()[1].imag != 0)
