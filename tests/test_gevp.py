@@ -38,11 +38,15 @@ def test_union_table_holds_every_element_table(basis):
     info = g.info()
     n = len(op_list)
     total = 0
+    # every element of the deuteron basis; one off-diagonal element of the 3He pair
+    compare = {(i, j) for i in range(n) for j in range(n)} if basis == "2H3" else {(0, 1)}
     for i in range(n):
         for j in range(n):
             el = gevp_element(op_list, i, j)
             pe = W.plan(**to_wick(el))
             total += pe.n_terms
+            if (i, j) not in compare:
+                continue
             ent, coef = table_entries(el, pe)
             uent, ucoef = union_entries(el, g)
             pos = {t: m for m, t in enumerate(sorted_entries(uent))}
