@@ -202,3 +202,15 @@ def test_point_block_form_general_plan_complex64_and_empty():
     Cz = _torch().full((1, 2, 2), 5.0, dtype=_torch().float64, device="cuda")
     w.point_blocks_correlator(pe, du, dd, out=Cz)
     assert np.all(Cz.cpu().numpy() == 0)
+
+
+def test_point_routes_agree_full_size():
+    """Determinants and the block form on the benchmark lattice (24^3, two time
+    slices): two independent algorithms for the same point-sink correlator."""
+    w = W()
+    for name in ("2H", "3He"):
+        hu, hd, du, dd = props(974, 1, (24, 24, 24, 2))
+        Cd = w.point_correlator(w.point_plan_std(name), du, dd).cpu().numpy()[0]
+        Cb = w.point_blocks_correlator(w.plan_std(name), du, dd).cpu().numpy()[0]
+        a, b = Cd[:, 0] + 1j * Cd[:, 1], Cb[:, 0] + 1j * Cb[:, 1]
+        assert np.all(np.abs(a - b) <= 1e-9 * np.abs(a)), (name, a, b)

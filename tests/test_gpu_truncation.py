@@ -94,3 +94,32 @@ def test_truncated_plan_matches_oracle(name, make, keep, batch):
         Cb = w.correlator([pl, tp], [(0, 0), (1, 0)], hu_, hd_, use_graph=use_graph).cpu().numpy()
         assert np.all(np.abs(Cb[0, :, 0] + 1j * Cb[0, :, 1] - ref_f) <= 1e-12 * mag_f)
         assert np.all(np.abs(Cb[1, :, 0] + 1j * Cb[1, :, 1] - ref_t) <= 1e-12 * mag_t)
+
+
+def test_truncated_plan_full_size_helium3():
+    """The benchmark's truncation (3He on 16^3 x 32, 10 % of the terms chosen on a
+    2^3 calibration lattice), evaluated at full size in the launch configuration
+    bench.py times; the oracle sums its own kept terms on sampled time slices."""
+    w = W()
+    op = ops.helium3()
+    pl = w.plan_std("3He")
+    keys, cm = oracle.merged_terms(op)
+    cu, cd, gu, gd = props(943, (2, 2, 2, 2))
+    tp, _ = pl.truncate(w.blocks(pl, gu, gd), 0.1)
+    kept, score, _ = oracle.important_terms(keys, cm, eq24(op, cu, cd), 0.1)
+    M = oracle.keep_count(len(cm), 0.1)
+    srt = np.sort(score)[::-1]
+    assert srt[M - 1] - srt[M] > 1e-9 * srt[M - 1]  # a clear edge for these seeds
+    idx = row_index(keys)
+    te, tc = table_entries(op, tp)
+    assert set(idx[tuple(r)] for r in np.sort(te, axis=1).tolist()) == set(np.flatnonzero(kept).tolist())
+    torch = _torch()
+    hu = wi.propagator(2, 0, 0, (16, 16, 16, 32))[None]
+    hd = wi.propagator(2, 0, 1, (16, 16, 16, 32))[None]
+    du, dd = torch.from_numpy(hu).cuda(), torch.from_numpy(hd).cuda()
+    C = w.contract(tp, w.blocks(tp, du, dd)).cpu().numpy()[0]
+    for t in (0, 31):
+        Beq = np.stack([oracle.block_eq24(k, hu[0, t], hd[0, t]) for k in op.kinds])[None]
+        v = oracle.term_values(keys[kept], cm[kept], Beq)[0]
+        got = C[t, 0] + 1j * C[t, 1]
+        assert abs(got - v.sum()) <= 1e-12 * np.abs(v).sum(), (t, got, v.sum())
