@@ -898,13 +898,21 @@ wick_status load_plan(const char *path, wick_plan_t *out)
     p->kinds.resize(K);
     for (auto &k : p->kinds) {
         int64_t nw;
-        for (int s = 0; s < 3; ++s) { int32_t v; if (!get(b, o, v)) return bad(); k.flav[s] = v; }
+        for (int s = 0; s < 3; ++s) {
+            int32_t v;
+            if (!get(b, o, v) || (v != 0 && v != 1)) return bad();
+            k.flav[s] = v;
+        }
+        // block kinds are nucleon-like: flavors (f, g, f) with g != f
+        if (k.flav[0] != k.flav[2] || k.flav[1] == k.flav[0]) return bad();
         if (!get(b, o, nw) || nw < 0 || nw > 1728) return bad();
         for (int64_t n = 0; n < nw; ++n) {
             std::array<int8_t, 3> j;
             GInt w;
-            for (int s = 0; s < 3; ++s) if (!get(b, o, j[s])) return bad();
+            for (int s = 0; s < 3; ++s)
+                if (!get(b, o, j[s]) || j[s] < 0 || j[s] > 11) return bad();
             if (!get(b, o, w.re) || !get(b, o, w.im)) return bad();
+            if (std::llabs(w.re) > (1LL << 20) || std::llabs(w.im) > (1LL << 20)) return bad();
             k.j.push_back(j);
             k.w.push_back(w);
         }

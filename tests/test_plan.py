@@ -310,3 +310,31 @@ def test_complex_coefficient_plan_matches_oracle():
     # the complex couplings multiply C by (1 + 2i)(2 - i) = 4 + 3i
     ref, _ = check_plan(op, W.plan_std("2H"), *small())
     assert abs(got - (4 + 3j) * ref) <= 1e-12 * 5 * mag
+
+
+def _fnv1a(b):
+    h = 1469598103934665603
+    for c in b:
+        h = ((h ^ c) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+@pytest.mark.parametrize("offset,value", [(64, 100), (52, 7), (48, 1)])
+def test_plan_file_with_valid_checksum_but_bad_kind_is_rejected(tmp_path, offset, value):
+    # a crafted file whose checksum matches: a spin-color index outside [0, 12),
+    # a flavor outside {0, 1}, slot flavors that are not (f, g, f)
+    import struct
+    pl = W.plan_std("2H")
+    path = tmp_path / "p.plan"
+    pl.save(path)
+    raw = bytearray(open(path, "rb").read())
+    body = raw[8:-8]
+    if offset == 64:
+        body[offset] = value                    # first weight's j1
+    else:
+        body[offset:offset + 4] = struct.pack("<i", value)  # a slot flavor of kind 0
+    out = bytes(raw[:8]) + bytes(body) + struct.pack("<Q", _fnv1a(bytes(body)))
+    open(path, "wb").write(out)
+    with pytest.raises(W.WickError) as e:
+        W.Plan.load(path)
+    assert e.value.status == W.ECORRUPT
