@@ -930,7 +930,7 @@ wick_status load_tune_file(const char *path)
             if (ok) tb[key] = t;
         } else if (ok && what == "contract") {
             int64_t v = 0;
-            ok = static_cast<bool>(is >> v) && v >= 1;
+            ok = static_cast<bool>(is >> v) && v >= 1 && v <= (1LL << 30);  // terms or chunks per workgroup
             if (ok) ts[key] = v;
         } else {
             ok = false;

@@ -298,6 +298,10 @@ def test_autotune_rejects_bad_arguments_and_corrupt_cache(tmp_path):
     with pytest.raises(W.WickError) as e:
         W.autotune(pl, (4, 4, 4, 8), cache_path=bad)
     assert e.value.status == W.ECORRUPT
+    bad.write_text("wick-tune 1\ncontract some:key 99999999999999\n")  # absurd slice length
+    with pytest.raises(W.WickError) as e:
+        W.autotune(pl, (4, 4, 4, 8), cache_path=bad)
+    assert e.value.status == W.ECORRUPT
 
 
 def test_complex_coefficient_plan_matches_oracle():
