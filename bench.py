@@ -643,9 +643,10 @@ def cpu_baseline(items, nuclei, hu, hd, plans, C_gpu):
 
 
 def same_table_cpu(pl):
-    """The deduplicated table itself evaluated on the host with numpy (gather,
-    product, sum; one thread), on random blocks of the plan's shape: the
-    method on the CPU, beside the oracle's own route."""
+    """The deduplicated table itself evaluated on the host, on random blocks of
+    the plan's shape: with numpy on one thread, and with the oracle's C loop on
+    all threads (the method on the CPU, beside the oracle's own route)."""
+    import oracle
     kidx, coef = pl.table()
     if kidx.shape[1] == 0:
         return None
@@ -662,8 +663,18 @@ def same_table_cpu(pl):
         if time.perf_counter() - t0 > 3.0:
             break
     dt = time.perf_counter() - t0
+    sets = np.stack([flat] * 8)
+    reps_c, t0 = 0, time.perf_counter()
+    while True:
+        oracle.table_sum(kidx, coef, sets)
+        reps_c += 8
+        if time.perf_counter() - t0 > 3.0:
+            break
+    dtc = time.perf_counter() - t0
     return {"value": reps * kidx.shape[1] / dt, "unit": "Wick terms/s", "threads": 1,
-            "sample": f"{reps} evaluation(s) of the {kidx.shape[1]}-term table"}
+            "sample": f"{reps} evaluation(s) of the {kidx.shape[1]}-term table with numpy",
+            "all_threads": {"value": reps_c * kidx.shape[1] / dtc, "threads": oracle.threads(),
+                            "sample": f"{reps_c} evaluation(s) of the table by a C loop (OpenMP)"}}
 
 
 if __name__ == "__main__":

@@ -72,6 +72,7 @@ def lib():
         L.oracle_threads.restype = ctypes.c_int32
         L.oracle_term_list.argtypes = [i32] + kinds + pats + [P, P]
         L.oracle_source_groups.argtypes = [i32] + kinds + [i32, P, P, i32, P, P]
+        L.oracle_table_sum.argtypes = [i32, i64, P, P, i32, i64, P, P]
         L.oracle_source_groups.restype = ctypes.c_long
         L.oracle_term_list.restype = ctypes.c_long
         _lib = L
@@ -361,3 +362,14 @@ def point_det_magnitude(op, Su, Sd, t_slices=None):
             A = du[ius][:, iuh] * dd[ids][:, idh]
             out[n] += aws @ A @ awh
     return abs(op.scale) * out
+
+
+def table_sum(kidx, coef, B_sets):
+    """sum_n coef_n prod_a B[s].flat[kidx[a, n]] for every block set s, on all
+    threads (a given flat table evaluated on the CPU; for timing beside the GPU)."""
+    kidx = np.ascontiguousarray(kidx, dtype=np.uint16)
+    coef = np.ascontiguousarray(coef, dtype=np.complex128)
+    B = np.ascontiguousarray(B_sets, dtype=np.complex128).reshape(len(B_sets), -1)
+    out = np.zeros((B.shape[0], 2))
+    lib().oracle_table_sum(kidx.shape[0], kidx.shape[1], _p(kidx), _p(coef), B.shape[0], B.shape[1], _p(B), _p(out))
+    return out[:, 0] + 1j * out[:, 1]

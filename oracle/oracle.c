@@ -699,6 +699,28 @@ long oracle_source_groups(int32_t A, int32_t K, const int32_t *flav, const int32
     return ng;
 }
 
+/* A flat table evaluated on given blocks, on all threads (the same-table CPU
+ * reference): out = sum_n coef_n prod_a B[kidx[a][n]] for each of n_sets
+ * block sets of K792 complex entries (kidx[A][N] as uint16, coef [N][2]). */
+void oracle_table_sum(int32_t A, int64_t N, const uint16_t *kidx, const double *coef_, int32_t n_sets,
+                      int64_t set_len, const double *B_, double *out)
+{
+    const cplx *coef = (const cplx *)coef_, *B = (const cplx *)B_;
+    for (int s = 0; s < n_sets; ++s) {
+        const cplx *Bs = B + (int64_t)s * set_len;
+        double sr = 0, si = 0;
+#pragma omp parallel for reduction(+ : sr, si) schedule(static)
+        for (int64_t n = 0; n < N; ++n) {
+            cplx p = coef[n];
+            for (int a = 0; a < A; ++a) p *= Bs[kidx[(int64_t)a * N + n]];
+            sr += creal(p);
+            si += cimag(p);
+        }
+        out[2 * s] = sr;
+        out[2 * s + 1] = si;
+    }
+}
+
 /* Number of OpenMP threads the oracle's parallel loops use. */
 int32_t oracle_threads(void)
 {
