@@ -481,16 +481,20 @@ def point_bench(args):
         torch.cuda.synchronize()
         dtb = (time.perf_counter() - t0) / args.steps
         W.profile(False)
-        nb, msb = W.profile_read("point_site_terms")
+        nb, msb = W.profile_read("point_site_blocks")
+        nc, msc = W.profile_read("contract")
         A, K, N = pl.info()
         nw = sum(len(pl.kind(k)[1]) for k in range(K))
         # per site: 28 flops per (block entry, weight) of the block build, 6A + 2 per term
-        f_site = 792 * nw * 28 + N * (6 * A + 2)
-        tf = f_site * slots / (msb / max(nb, 1) * 1e-3) / 1e12
+        tf_b = 792 * nw * 28 * slots / (msb / args.steps * 1e-3) / 1e12
+        tf_c = N * (6 * A + 2) * slots / (msc / args.steps * 1e-3) / 1e12
         cb, cd = Cb.cpu().numpy()[0], C.cpu().numpy()[0]
         dev = np.max(np.abs((cb[:, 0] - cd[:, 0]) + 1j * (cb[:, 1] - cd[:, 1])) / np.abs(cd[:, 0] + 1j * cd[:, 1]))
         out["block_form"] = {"ms_per_step": 1e3 * dtb, "s_per_time_slice": dtb / T, "speedup_vs_determinants": step_s / dtb,
-                             "table_terms": N, "kernel": "pt_site_terms_kernel", "achieved_TFLOPs": tf, "frac_fp64_alu": tf / 78.6,
+                             "table_terms": N, "terms_per_s": N * slots / dtb,
+                             "site_blocks_kernel": {"ms_per_step": msb / args.steps, "TFLOPs": tf_b, "frac_fp64_alu": tf_b / 78.6},
+                             "term_sum": {"kernel": "contract_tg_kernel", "ms_per_step": msc / args.steps, "TFLOPs": tf_c,
+                                          "frac_fp64_alu": tf_c / 78.6},
                              "max_rel_diff_vs_determinants": float(dev)}
     if not args.no_cpu_baseline:
         note("cpu baseline (oracle point route)")

@@ -301,11 +301,13 @@ void wick_point_destroy(wick_point_t plan);
 /* The same point-sink correlator in the block form (Eq. 3.1): at every site
  * the blocks of that site alone and the plane-wave plan's signed term table
  * on them, summed over sites (C[cfg][t] = sum_x sum_n coef_n prod_a
- * B_x[kidx_{a,n}], scale included). One fused kernel per call; the
- * cheaper route when the table is small (A <= 3), the determinant route
- * for helium-4. Same arguments and errors as wick_point_correlator, with a
- * plan from wick_plan / wick_plan_std; WICK_EUNSUPPORTED above 11 block
- * kinds. */
+ * B_x[kidx_{a,n}], scale included). The per-site blocks are built in chunks
+ * of site-slices and summed with the wick_contract kernels (the site-slices
+ * take the place of time slices). On the 24^3 lattice it is the faster route
+ * for deuteron and helium-3, the determinant route for helium-4. Same
+ * arguments and errors as wick_point_correlator, with a plan from wick_plan /
+ * wick_plan_std; it allocates a second per-stream workspace for the site
+ * blocks (at most 512 MB) and the per-site sums. */
 wick_status wick_point_blocks_correlator(wick_plan_t plan, const void *S_u, const void *S_d, wick_dtype dtype,
                                          const int32_t dims[4], int32_t n_cfg, wick_stream_t stream, double *C);
 

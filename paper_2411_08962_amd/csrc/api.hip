@@ -13,6 +13,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.hpp"
@@ -47,22 +48,24 @@ struct Workspace {
     size_t bytes = 0;
 };
 std::mutex g_ws_mu;
-std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+std::map<std::tuple<int, hipStream_t, int>, Workspace> g_ws;  // (device, stream, tag)
 wick_status ws_hip_fail(hipError_t e, const char *what)
 {
     return fail(WICK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 }  // namespace
 
-// A device buffer of at least `bytes` private to (device, stream). Growing it
-// waits for the stream, so earlier work that used the old buffer is done.
-wick_status workspace(hipStream_t s, size_t bytes, void **out)
+// A device buffer of at least `bytes` private to (device, stream, tag). Growing
+// it waits for the stream, so earlier work that used the old buffer is done.
+// Tag 0 serves the block and term-sum launches; other tags hold buffers that
+// must stay alive across such launches.
+wick_status workspace(hipStream_t s, size_t bytes, void **out, int tag)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return ws_hip_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_ws_mu);
-    Workspace &w = g_ws[{dev, s}];
+    Workspace &w = g_ws[std::make_tuple(dev, s, tag)];
     if (w.bytes < bytes) {
         if (w.ptr) {
             e = hipStreamSynchronize(s);
@@ -80,6 +83,8 @@ wick_status workspace(hipStream_t s, size_t bytes, void **out)
     return WICK_OK;
 }
 
+wick_status workspace(hipStream_t s, size_t bytes, void **out) { return workspace(s, bytes, out, 0); }
+
 namespace {
 
 void release_workspace(hipStream_t s)
@@ -87,11 +92,16 @@ void release_workspace(hipStream_t s)
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return;
     std::lock_guard<std::mutex> lk(g_ws_mu);
-    auto it = g_ws.find({dev, s});
-    if (it == g_ws.end()) return;
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(it->second.ptr);
-    g_ws.erase(it);
+    bool synced = false;
+    for (auto it = g_ws.begin(); it != g_ws.end();) {
+        if (std::get<0>(it->first) == dev && std::get<1>(it->first) == s) {
+            if (!synced) { (void)hipStreamSynchronize(s); synced = true; }
+            (void)hipFree(it->second.ptr);
+            it = g_ws.erase(it);
+        } else {
+            ++it;
+        }
+    }
 }
 
 // ---------------------------------------------------------- device tables
@@ -1340,8 +1350,8 @@ wick_status wick_shutdown(void)
     int cur = 0;
     (void)hipGetDevice(&cur);
     for (auto &kv : g_ws) {
-        (void)hipSetDevice(kv.first.first);
-        (void)hipStreamSynchronize(kv.first.second);
+        (void)hipSetDevice(std::get<0>(kv.first));
+        (void)hipStreamSynchronize(std::get<1>(kv.first));
         (void)hipFree(kv.second.ptr);
     }
     (void)hipSetDevice(cur);

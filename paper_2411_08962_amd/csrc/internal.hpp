@@ -55,12 +55,9 @@ struct NucGroup {
     std::vector<int> kinds, alpha;             // block-kind indices and their sink spins
 };
 
-// Plain table and kind weights on one device, for the per-site point-sink
-// route (point.hip).
+// Kind weights on one device, for the per-site point-sink route (point.hip).
 struct DeviceTable {
     int device = -1;
-    void *kidx = nullptr;   // uint16 [A][n_terms]
-    void *coef = nullptr;   // double [n_terms] (real) or [n_terms][2]
     void *kinds = nullptr;  // per-kind flavors and weight offsets, then the weights
 };
 
@@ -79,7 +76,7 @@ struct wick_plan_s {
     bool coef_real = true;
     int64_t n_enumerated = 0, n_groups = 0;
     double bound = 0.0, scale = 1.0;
-    // plain device copies of the table for the per-site point-sink route, one per device
+    // device copies of the kind weights for the per-site point-sink route, one per device
     std::mutex dev_mu;
     std::vector<wick::DeviceTable> dev;
     ~wick_plan_s();

@@ -39,6 +39,7 @@
 namespace wick {
 
 wick_status workspace(hipStream_t s, size_t bytes, void **out);
+wick_status workspace(hipStream_t s, size_t bytes, void **out, int tag);
 
 namespace {
 
@@ -305,105 +306,51 @@ __global__ __launch_bounds__(kPtThreads) void pt_reduce_kernel(const double2 *__
 
 // ---------------------------------------------- point sinks from site blocks
 // The point-sink correlator in the block form (Eq. 3.1): at every site the
-// blocks of that site alone, then the plan's signed term table on them,
-// summed over sites. pt_site_terms_kernel: a workgroup takes S site-slices;
-// it stages their propagators, builds every kind's compact block of each
-// site in LDS (the antisymmetrised sum over the kind's weights), then every
-// thread evaluates its share of the table on all S sites. One partial per
-// site-slice; pt_reduce_kernel sums the sites of each (configuration, t).
-constexpr int kPbThreads = 512;
+// blocks of that site alone, contracted with the plan's signed term table,
+// summed over sites. pt_site_blocks_kernel writes the compact blocks of every
+// kind for a chunk of site-slices (one workgroup per site-slice: the
+// antisymmetrised sum over the kind's weights); the term sum over each
+// site-slice is then the plane-wave term-sum kernel with site-slices in place
+// of time slices, and pt_reduce_kernel sums the sites of each (configuration, t).
+constexpr int kPbThreads = 256;
 
 struct PbKind {
     int32_t f, g, n_w, off;  // slot flavors (f, g, f), weights [off, off + n_w)
 };
 
-struct PbArgs {
-    const PbKind *kinds;
-    const int8_t *wj;    // [total weights][3]
-    const double2 *ww;   // [total weights]
-    int K, A;
-    const uint16_t *kidx;
-    const double *coef;  // real [N] or complex [N][2]
-    int64_t N;
-    int64_t n_slots;
-};
-
-template <typename TIn, int S, bool REAL>
-__global__ __launch_bounds__(kPbThreads) void pt_site_terms_kernel(const TIn *__restrict__ Su,
-                                                                  const TIn *__restrict__ Sd, PbArgs a,
-                                                                  double2 *__restrict__ partial)
+template <typename TIn>
+__global__ __launch_bounds__(kPbThreads) void pt_site_blocks_kernel(const TIn *__restrict__ Su,
+                                                                   const TIn *__restrict__ Sd, const PbKind *kinds,
+                                                                   const double2 *__restrict__ ww,
+                                                                   const int8_t *__restrict__ wj, int K, int64_t slot0,
+                                                                   double2 *__restrict__ Bout)
 {
-    extern __shared__ double2 lds[];
-    double2 *sS = lds;                // [S][2][144]
-    double2 *sB = lds + S * 288;      // [S][K * 792]
-    __shared__ double2 red[kPbThreads / 64][S];
-    const int64_t slot0 = (int64_t)blockIdx.x * S;
-    const int ns = (int)min((int64_t)S, a.n_slots - slot0);
-    for (int e = threadIdx.x; e < S * 288; e += kPbThreads) {
-        const int s = e / 288, r = e % 288, fl = r / 144, q = r % 144;
-        double2 v = make_double2(0.0, 0.0);
-        if (s < ns) {
-            const TIn *src = (fl == 0 ? Su : Sd) + (slot0 + s) * 144 + q;
-            v = make_double2((double)src->x, (double)src->y);
-        }
-        sS[e] = v;
+    __shared__ double2 sS[288];
+    const int64_t slot = slot0 + blockIdx.x;
+    for (int e = threadIdx.x; e < 288; e += kPbThreads) {
+        const TIn *src = (e < 144 ? Su : Sd) + slot * 144 + e % 144;
+        sS[e] = make_double2((double)src->x, (double)src->y);
     }
     __syncthreads();
-    const int KB = a.K * 792;
-    for (int e = threadIdx.x; e < S * KB; e += kPbThreads) {
-        const int s = e / KB, r = e % KB, k = r / 792, c = r % 792;
+    double2 *out = Bout + (int64_t)blockIdx.x * K * 792;
+    for (int e = threadIdx.x; e < K * 792; e += kPbThreads) {
+        const int k = e / 792, c = e % 792;
         const int pair = c / 12, i2 = c % 12;
         int i3 = 1;
         while ((i3 + 1) * i3 / 2 <= pair) ++i3;
         const int i1 = pair - i3 * (i3 - 1) / 2;
-        const PbKind kd = a.kinds[k];
-        const double2 *F = sS + s * 288 + kd.f * 144, *G = sS + s * 288 + kd.g * 144;
+        const PbKind kd = kinds[k];
+        const double2 *F = sS + kd.f * 144, *G = sS + kd.g * 144;
         double2 acc = make_double2(0.0, 0.0);
         for (int w = kd.off; w < kd.off + kd.n_w; ++w) {
-            const int j1 = a.wj[3 * w], j2 = a.wj[3 * w + 1], j3 = a.wj[3 * w + 2];
+            const int j1 = wj[3 * w], j2 = wj[3 * w + 1], j3 = wj[3 * w + 2];
             const double2 x = cmul(F[j1 * 12 + i1], F[j3 * 12 + i3]);
             const double2 y = cmul(F[j1 * 12 + i3], F[j3 * 12 + i1]);
-            const double2 t = cmul(a.ww[w], cmul(G[j2 * 12 + i2], make_double2(x.x - y.x, x.y - y.y)));
+            const double2 t = cmul(ww[w], cmul(G[j2 * 12 + i2], make_double2(x.x - y.x, x.y - y.y)));
             acc.x += t.x;
             acc.y += t.y;
         }
-        sB[e] = acc;
-    }
-    __syncthreads();
-    double2 acc[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) acc[s] = make_double2(0.0, 0.0);
-    for (int64_t n = threadIdx.x; n < a.N; n += kPbThreads) {
-        int idx[kMaxA];
-#pragma unroll
-        for (int q = 0; q < kMaxA; ++q) idx[q] = q < a.A ? a.kidx[(int64_t)q * a.N + n] : 0;
-        const double2 c = REAL ? make_double2(a.coef[n], 0.0) : make_double2(a.coef[2 * n], a.coef[2 * n + 1]);
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const double2 *B = sB + s * KB;
-            double2 p = B[idx[0]];
-#pragma unroll
-            for (int q = 1; q < kMaxA; ++q)
-                if (q < a.A) p = cmul(p, B[idx[q]]);
-            const double2 t = REAL ? make_double2(c.x * p.x, c.x * p.y) : cmul(c, p);
-            acc[s].x += t.x;
-            acc[s].y += t.y;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        double2 v = acc[s];
-        for (int o = 32; o > 0; o >>= 1) {
-            v.x += __shfl_down(v.x, o, 64);
-            v.y += __shfl_down(v.y, o, 64);
-        }
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][s] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < ns) {
-        double2 v = red[0][threadIdx.x];
-        for (int w = 1; w < kPbThreads / 64; ++w) { v.x += red[w][threadIdx.x].x; v.y += red[w][threadIdx.x].y; }
-        partial[slot0 + threadIdx.x] = v;
+        out[e] = acc;
     }
 }
 
@@ -615,9 +562,9 @@ wick_status launch_point(wick_point_s *p, PtDev *d, const TIn *Su, const TIn *Sd
     return e == hipSuccess ? WICK_OK : pt_hip_fail(e, "pt_reduce_kernel");
 }
 
-// The plan's plain table and kind weights on the current device (cached in
-// the plan, released with it).
-wick_status plain_tables(wick_plan_s *p, DeviceTable *out)
+// The plan's kind weights on the current device (cached in the plan, released
+// with it): the kinds, then the weights (16-byte aligned), then their indices.
+wick_status kind_tables(wick_plan_s *p, DeviceTable *out)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -639,31 +586,15 @@ wick_status plain_tables(wick_plan_s *p, DeviceTable *out)
             ww.push_back(make_double2((double)kd.w[n].re, (double)kd.w[n].im));
         }
     }
-    // one buffer: kinds, then weights (16-byte aligned), then weight indices
     const size_t kb = ((K * sizeof(PbKind)) + 15) / 16 * 16, wb = ww.size() * sizeof(double2);
     std::vector<char> blob(kb + wb + wj.size() + 16, 0);
     std::memcpy(blob.data(), kinds.data(), K * sizeof(PbKind));
     std::memcpy(blob.data() + kb, ww.data(), wb);
     std::memcpy(blob.data() + kb + wb, wj.data(), wj.size());
-    const size_t N = (size_t)p->n_terms;
-    std::vector<double> coef(p->coef_real ? N : 2 * N);
-    for (size_t n = 0; n < N; ++n) {
-        if (p->coef_real) coef[n] = p->coef_re[n];
-        else { coef[2 * n] = p->coef_re[n]; coef[2 * n + 1] = p->coef_im[n]; }
-    }
-    const size_t ib = std::max<size_t>(1, p->kidx.size()) * sizeof(uint16_t), cb = std::max<size_t>(1, coef.size()) * 8;
-    if ((e = hipMalloc(&d.kinds, blob.size())) != hipSuccess || (e = hipMalloc(&d.kidx, ib)) != hipSuccess ||
-        (e = hipMalloc(&d.coef, cb)) != hipSuccess) {
-        (void)hipFree(d.kinds);
-        (void)hipFree(d.kidx);
+    if ((e = hipMalloc(&d.kinds, blob.size())) != hipSuccess)
         return fail(WICK_ENOMEM, std::string("wick_point_blocks_correlator: hipMalloc: ") + hipGetErrorString(e));
-    }
-    if ((e = hipMemcpy(d.kinds, blob.data(), blob.size(), hipMemcpyHostToDevice)) != hipSuccess ||
-        (!p->kidx.empty() && (e = hipMemcpy(d.kidx, p->kidx.data(), p->kidx.size() * 2, hipMemcpyHostToDevice)) != hipSuccess) ||
-        (!coef.empty() && (e = hipMemcpy(d.coef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)) {
+    if ((e = hipMemcpy(d.kinds, blob.data(), blob.size(), hipMemcpyHostToDevice)) != hipSuccess) {
         (void)hipFree(d.kinds);
-        (void)hipFree(d.kidx);
-        (void)hipFree(d.coef);
         return pt_hip_fail(e, "wick_point_blocks_correlator: hipMemcpy");
     }
     p->dev.push_back(d);
@@ -671,42 +602,9 @@ wick_status plain_tables(wick_plan_s *p, DeviceTable *out)
     return WICK_OK;
 }
 
-template <typename TIn, int S>
-void launch_site_terms(bool real, dim3 grid, size_t shmem, hipStream_t s, const TIn *Su, const TIn *Sd,
-                       const PbArgs &a, double2 *partial)
-{
-    if (real) pt_site_terms_kernel<TIn, S, true><<<grid, kPbThreads, shmem, s>>>(Su, Sd, a, partial);
-    else pt_site_terms_kernel<TIn, S, false><<<grid, kPbThreads, shmem, s>>>(Su, Sd, a, partial);
-}
-
 template <typename TIn>
-wick_status set_site_terms_lds(int S, size_t shmem)
-{
-    hipError_t e = hipSuccess;
-    const int v = (int)shmem;
-    switch (S) {
-    case 1:
-        if ((e = hipFuncSetAttribute((const void *)pt_site_terms_kernel<TIn, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) != hipSuccess ||
-            (e = hipFuncSetAttribute((const void *)pt_site_terms_kernel<TIn, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) != hipSuccess)
-            return pt_hip_fail(e, "hipFuncSetAttribute");
-        break;
-    case 2:
-        if ((e = hipFuncSetAttribute((const void *)pt_site_terms_kernel<TIn, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) != hipSuccess ||
-            (e = hipFuncSetAttribute((const void *)pt_site_terms_kernel<TIn, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) != hipSuccess)
-            return pt_hip_fail(e, "hipFuncSetAttribute");
-        break;
-    default:
-        if ((e = hipFuncSetAttribute((const void *)pt_site_terms_kernel<TIn, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) != hipSuccess ||
-            (e = hipFuncSetAttribute((const void *)pt_site_terms_kernel<TIn, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, v)) != hipSuccess)
-            return pt_hip_fail(e, "hipFuncSetAttribute");
-        break;
-    }
-    return WICK_OK;
-}
-
-template <typename TIn>
-wick_status launch_point_blocks(wick_plan_s *p, const DeviceTable *d, const TIn *Su, const TIn *Sd, int64_t V, int64_t n_ct,
-                                hipStream_t s, double2 *C)
+wick_status launch_point_blocks(wick_plan_s *p, const DeviceTable *d, const TIn *Su, const TIn *Sd, int64_t V,
+                                int64_t n_ct, hipStream_t s, double2 *C)
 {
     const int64_t slots = V * n_ct;
     if (p->n_terms == 0) {
@@ -714,43 +612,35 @@ wick_status launch_point_blocks(wick_plan_s *p, const DeviceTable *d, const TIn 
         return e == hipSuccess ? WICK_OK : pt_hip_fail(e, "zero_kernel");
     }
     const int K = (int)p->kinds.size();
-    const size_t per_site = (size_t)(288 + K * 792) * sizeof(double2);
-    constexpr size_t kLds = 152 * 1024;
-    const int S = per_site * 4 <= kLds ? 4 : per_site * 2 <= kLds ? 2 : 1;
-    const size_t shmem = per_site * S;
-    if (shmem > kLds) return fail(WICK_EUNSUPPORTED, "wick_point_blocks_correlator: too many block kinds for LDS");
+    const size_t per_slot = (size_t)K * 792 * sizeof(double2);
+    // site-slices per chunk: at most 512 MB of blocks and at most 2^20 sets per term-sum call
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>({slots, (int64_t)((512ull << 20) / per_slot), 1 << 20}));
     void *ws = nullptr;
-    wick_status st = workspace(s, (size_t)slots * sizeof(double2), &ws);
+    const size_t c_off = ((size_t)chunk * per_slot + 255) / 256 * 256;
+    wick_status st = workspace(s, c_off + (size_t)slots * sizeof(double2), &ws, 1);
     if (st != WICK_OK) return st;
-    if (shmem > 64 * 1024 && (st = set_site_terms_lds<TIn>(S, shmem)) != WICK_OK) return st;
-    PbArgs a{};
-    const size_t kb = ((K * sizeof(PbKind)) + 15) / 16 * 16;
+    double2 *Bw = (double2 *)ws, *Cs = (double2 *)((char *)ws + c_off);
     size_t nw = 0;
     for (auto &kd : p->kinds) nw += kd.w.size();
-    a.kinds = (const PbKind *)d->kinds;
-    a.ww = (const double2 *)((const char *)d->kinds + kb);
-    a.wj = (const int8_t *)((const char *)d->kinds + kb + nw * sizeof(double2));
-    a.K = K;
-    a.A = p->A;
-    a.kidx = (const uint16_t *)d->kidx;
-    a.coef = (const double *)d->coef;
-    a.N = p->n_terms;
-    a.n_slots = slots;
-    double2 *partial = (double2 *)ws;
-    const int64_t nwg = (slots + S - 1) / S;
-    if (nwg > (1LL << 31) - 1) return fail(WICK_ETOOBIG, "wick_point_blocks_correlator: lattice too large");
-    const dim3 grid((unsigned)nwg);
-    Probe pr("point_site_terms", s);
-    if (S == 4) launch_site_terms<TIn, 4>(p->coef_real, grid, shmem, s, Su, Sd, a, partial);
-    else if (S == 2) launch_site_terms<TIn, 2>(p->coef_real, grid, shmem, s, Su, Sd, a, partial);
-    else launch_site_terms<TIn, 1>(p->coef_real, grid, shmem, s, Su, Sd, a, partial);
-    pr.stop();
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return pt_hip_fail(e, "pt_site_terms_kernel");
+    const size_t kb = ((K * sizeof(PbKind)) + 15) / 16 * 16;
+    const PbKind *kinds = (const PbKind *)d->kinds;
+    const double2 *ww = (const double2 *)((const char *)d->kinds + kb);
+    const int8_t *wj = (const int8_t *)((const char *)d->kinds + kb + nw * sizeof(double2));
+    for (int64_t s0 = 0; s0 < slots; s0 += chunk) {
+        const int64_t n = std::min<int64_t>(chunk, slots - s0);
+        Probe pb("point_site_blocks", s);
+        pt_site_blocks_kernel<TIn><<<dim3((unsigned)n), dim3(kPbThreads), 0, s>>>(Su, Sd, kinds, ww, wj, K, s0, Bw);
+        pb.stop();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return pt_hip_fail(e, "pt_site_blocks_kernel");
+        // the plane-wave term sum, one set per site-slice
+        if ((st = wick_contract(p, (const double *)Bw, 1, (int32_t)n, (wick_stream_t)s, (double *)(Cs + s0))) != WICK_OK)
+            return st;
+    }
     Probe pc("point_reduce", s);
-    pt_reduce_kernel<<<dim3((unsigned)n_ct), dim3(kPtThreads), 0, s>>>(partial, V, 1.0, C);
+    pt_reduce_kernel<<<dim3((unsigned)n_ct), dim3(kPtThreads), 0, s>>>(Cs, V, 1.0, C);
     pc.stop();
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     return e == hipSuccess ? WICK_OK : pt_hip_fail(e, "pt_reduce_kernel");
 }
 
@@ -779,8 +669,6 @@ void release_plain_tables(wick_plan_s *p)
         (void)hipSetDevice(d.device);
         (void)hipDeviceSynchronize();
         (void)hipFree(d.kinds);
-        (void)hipFree(d.kidx);
-        (void)hipFree(d.coef);
     }
     p->dev.clear();
     (void)hipSetDevice(cur);
@@ -804,7 +692,7 @@ extern "C" wick_status wick_point_blocks_correlator(wick_plan_t p, const void *S
         if (V < 0) return fail(WICK_ETOOBIG, "wick_point_blocks_correlator: lattice too large");
         const int64_t n_ct = (int64_t)n_cfg * dims[3];
         DeviceTable d;
-        wick_status st = plain_tables(p, &d);
+        wick_status st = kind_tables(p, &d);
         if (st != WICK_OK) return st;
         hipStream_t s = (hipStream_t)stream;
         if (dtype == WICK_C128)
