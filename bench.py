@@ -85,7 +85,8 @@ def block_flops_per_site(nucleus):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp"):
+    # the kernels, and the host code that picks table forms and launch shapes
+    for f in ("kernels.hip", "kernels.hpp", "api.hip"):
         h.update(open(os.path.join(ROOT, "paper_2411_08962_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -487,15 +487,15 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
         }
     }
     const size_t nt = (size_t)p->n_terms;
-    // table form: segmented for A = 4 (where sharing the leading indices
-    // pays: 22 % faster on 4He), packed for A <= 3, plain otherwise;
-    // WICK_TABLE_FORM=plain|packed|segmented selects one (testing)
+    // table form: segmented for A >= 3 (sharing the leading indices pays:
+    // 22 % faster than packed on 4He, 31 % on 3He), packed for A = 2, plain
+    // when neither fits; WICK_TABLE_FORM=plain|packed|segmented selects one (testing)
     const char *form_env = std::getenv("WICK_TABLE_FORM");
     const std::string form = form_env ? form_env : "";
     std::vector<uint64_t> words;
     std::vector<double2> pal;
     SegTable seg;
-    const bool segmented = (form == "segmented" || (form.empty() && p->A >= 4)) && segment_table(p, seg);
+    const bool segmented = (form == "segmented" || (form.empty() && p->A >= 3)) && segment_table(p, seg);
     const bool packed = !segmented && (form.empty() || form == "packed") && pack_table(p, words, pal);
     if (segmented) {
         words.swap(seg.words);
