@@ -293,7 +293,10 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_f64_staged_kernel(
 // as colour cross products per nonzero diquark-matrix entry (6 LDS loads for
 // all three rows) and Aop read with a per-lane base offset fixed at kernel
 // start. The GEMM runs, by MODE, on
-//   P64: v_mfma_f64_16x16x4f64 (four real MFMAs per complex product);
+//   P64: v_mfma_f64_16x16x4f64, three real MFMAs per complex product
+//        (Gauss): with E = a + ib and Aop = c + id, K1 += (a + b) c,
+//        K2 += a (d - c), K3 += b (c + d), then Re = K1 - K3, Im = K1 + K2,
+//        formed once per workgroup after the site loop;
 //   P32: v_mfma_f32_16x16x4f32 with E and Aop rounded to FP32;
 //   PB3: v_mfma_f32_16x16x32_bf16, E and Aop split into two BF16 limbs
 //        (hi + lo), the three products hi*hi + hi*lo + lo*hi packed along K:
@@ -410,9 +413,11 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
             bo[t] = (G.flv[kk] ? (G.g - G.f) * kNucSites * 144 : 0) + 36 * G.alpha[kk] + m % 12;
         }
     }
-    d4 acc[NT][2];
+    // P64: acc[t] = (K1, K2) and acc3[t] = K3 of the three-product form;
+    // the split modes: (Re, Im) in FP64
+    d4 acc[NT][2], acc3[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t][0] = acc[t][1] = d4{0, 0, 0, 0};
+    for (int t = 0; t < NT; ++t) acc[t][0] = acc[t][1] = acc3[t] = d4{0, 0, 0, 0};
 
     const int64_t x0 = (int64_t)chunk * chunk_sites;
     const int64_t x1 = x0 + chunk_sites < V ? x0 + chunk_sites : V;
@@ -532,15 +537,14 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
                     const double ex = r == 0 ? e0x : (r == 1 ? e1x : e2x);
                     const double ey = r == 0 ? e0y : (r == 1 ? e1y : e2y);
                     if constexpr (MODE == WICK_P64) {
-                        const double ney = -ey;
+                        const double exy = ex + ey;
 #pragma unroll
                         for (int t = 0; t < NT; ++t) {
                             if (tgroup[t] != g) continue;
                             const double2 v = rd(sfb + bo[t] + 12 * r);
-                            acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, v.x, acc[t][0], 0, 0, 0);
-                            acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, v.y, acc[t][1], 0, 0, 0);
-                            acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ney, v.y, acc[t][0], 0, 0, 0);
-                            acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey, v.x, acc[t][1], 0, 0, 0);
+                            acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(exy, v.x, acc[t][0], 0, 0, 0);
+                            acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, v.y - v.x, acc[t][1], 0, 0, 0);
+                            acc3[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey, v.x + v.y, acc3[t], 0, 0, 0);
                         }
                     } else if constexpr (MODE == WICK_P32) {
                         const float fx = (float)(ex * scE), fy = (float)(ey * scE);
@@ -624,6 +628,17 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
         batch(sbuf1);
         wait_staged();
         __syncthreads();
+    }
+    if constexpr (MODE == WICK_P64) {
+        // (K1, K2, K3) -> (Re, Im) = (K1 - K3, K1 + K2)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double k1 = acc[t][0][v];
+                acc[t][0][v] = k1 - acc3[t][v];
+                acc[t][1][v] = k1 + acc[t][1][v];
+            }
     }
     // sum the four site phases in a fixed order through LDS (the staging
     // buffers are free now): ((phase 3 + phase 2) + phase 1) + phase 0
