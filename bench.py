@@ -36,7 +36,7 @@ WORKLOADS = {
     "7Li-32^3x64": ((32, 32, 32, 64), 1, "c128", 4, [("4He", 0), ("3H", 0)], "p32"),
     "batch64-16^3x32": ((16, 16, 16, 32), 64, "c64", 5,
                         [("2H", c) for c in range(8)] + [("3He", c) for c in range(8, 32)]
-                        + [("4He", c) for c in range(32, 64)], "p32"),
+                        + [("4He", c) for c in range(32, 64)], "p64"),
 }
 DEFAULT = "3He-16^3x32"
 

@@ -89,9 +89,9 @@ def test_lithium7_clusters_32cubed_x64():
 
 def test_batch64_mixed_nuclei_c64_graph():
     """64 complex64 configurations of 16^3 x 32: 2H on 0-7, 3He on 8-31, 4He on
-    32-63, one graph-captured batch with FP32 blocks; sampled items against the
-    oracle (which reads the same complex64 values), and a second replay equal
-    to the first bitwise."""
+    32-63, one graph-captured batch with FP32 and with FP64 blocks; sampled
+    items against the oracle (which reads the same complex64 values), and for
+    each precision a second replay equal to the first bitwise."""
     import torch
     import paper_2411_08962_amd as w
     names = ["2H", "3He", "4He"]
@@ -99,15 +99,18 @@ def test_batch64_mixed_nuclei_c64_graph():
     items = [(0, c) for c in range(8)] + [(1, c) for c in range(8, 32)] + [(2, c) for c in range(32, 64)]
     hu, hd, du, dd = props(5, 64, (16, 16, 16, 32), np.complex64)
     out = torch.empty((64, 32, 2), dtype=torch.float64, device="cuda")
-    w.correlator(plans, items, du, dd, "p32", use_graph=True, out=out)
-    torch.cuda.synchronize()
-    first = out.cpu().numpy()
-    out.zero_()
-    w.correlator(plans, items, du, dd, "p32", use_graph=True, out=out)
-    torch.cuda.synchronize()
-    assert np.array_equal(out.cpu().numpy(), first)
+    got = {}
+    for prec in ("p32", "p64"):
+        w.correlator(plans, items, du, dd, prec, use_graph=True, out=out)
+        torch.cuda.synchronize()
+        got[prec] = out.cpu().numpy()
+        out.zero_()
+        w.correlator(plans, items, du, dd, prec, use_graph=True, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), got[prec]), prec
     for i, t in ((3, 0), (3, 31), (17, 5), (40, 0), (63, 31)):
         name = names[items[i][0]]
         ref, mag = reference(name, hu, hd, items[i][1], t)
-        got = first[i, t, 0] + 1j * first[i, t, 1]
-        assert abs(got - ref) <= TOL["p32"] * mag, (i, name, t, abs(got - ref) / mag)
+        for prec, C in got.items():
+            c = C[i, t, 0] + 1j * C[i, t, 1]
+            assert abs(c - ref) <= TOL[prec] * mag, (prec, i, name, t, abs(c - ref) / mag)
