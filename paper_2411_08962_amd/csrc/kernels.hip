@@ -538,13 +538,17 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
                     const double ey = r == 0 ? e0y : (r == 1 ? e1y : e2y);
                     if constexpr (MODE == WICK_P64) {
                         const double exy = ex + ey;
+                        // every tile's entry first (a tile of another group reads
+                        // offset 0, inside the buffer), then the MFMAs
+                        double2 v[NT];
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) v[t] = rd(sfb + (tgroup[t] == g ? bo[t] : 0) + 12 * r);
 #pragma unroll
                         for (int t = 0; t < NT; ++t) {
                             if (tgroup[t] != g) continue;
-                            const double2 v = rd(sfb + bo[t] + 12 * r);
-                            acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(exy, v.x, acc[t][0], 0, 0, 0);
-                            acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, v.y - v.x, acc[t][1], 0, 0, 0);
-                            acc3[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey, v.x + v.y, acc3[t], 0, 0, 0);
+                            acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(exy, v[t].x, acc[t][0], 0, 0, 0);
+                            acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ex, v[t].y - v[t].x, acc[t][1], 0, 0, 0);
+                            acc3[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey, v[t].x + v[t].y, acc3[t], 0, 0, 0);
                         }
                     } else if constexpr (MODE == WICK_P32) {
                         const float fx = (float)(ex * scE), fy = (float)(ey * scE);
