@@ -552,12 +552,17 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
                         }
                     } else if constexpr (MODE == WICK_P32) {
                         const float fx = (float)(ex * scE), fy = (float)(ey * scE);
+                        // every tile's entry first (a tile of another group reads
+                        // offset 0, inside the buffer), then the MFMAs
                         float2 v[NT];
 #pragma unroll
                         for (int t = 0; t < NT; ++t) {
-                            if (tgroup[t] != g) continue;
-                            const double2 d = rd(sfb + bo[t] + 12 * r);
+                            const double2 d = rd(sfb + (tgroup[t] == g ? bo[t] : 0) + 12 * r);
                             v[t] = float2{(float)(d.x * scA), (float)(d.y * scA)};
+                        }
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) {
+                            if (tgroup[t] != g) continue;
                             acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fx, v[t].x, acc32[t][0], 0, 0, 0);
                             acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fx, v[t].y, acc32[t][1], 0, 0, 0);
                         }
