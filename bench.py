@@ -8,11 +8,14 @@ starts.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision p64]
 
-Workloads: 2H-4^3x8 (small case), 3He-16^3x32 (default), 4He-24^3x48,
-7Li-32^3x64 (the 4He and 3H cluster correlators, batched), batch64-16^3x32
-(64 complex64 configurations: 8 2H, 24 3He, 32 4He correlators in one
-graph-captured batch). Prints one JSON line. Only the ``cpu_baseline`` leg
-uses the oracle.
+Workloads: batch64-16^3x32 (default: 64 complex64 configurations, 8 2H,
+24 3He and 32 4He correlators in one graph-captured batch), 2H-4^3x8 (small
+case), 3He-16^3x32, 4He-24^3x48, 7Li-32^3x64 (the 4He and 3H cluster
+correlators, batched). ``value`` is the FP64 path; the split-precision modes
+are timed beside it on the same inputs, and every precision's C(t) is
+compared with the oracle on sampled (correlator, time slice) pairs. Prints
+one JSON line. Only the oracle legs (``cpu_baseline`` and the sampled
+reference values) use the oracle.
 """
 import argparse
 import hashlib
@@ -38,7 +41,7 @@ WORKLOADS = {
                         [("2H", c) for c in range(8)] + [("3He", c) for c in range(8, 32)]
                         + [("4He", c) for c in range(32, 64)], "p64"),
 }
-DEFAULT = "3He-16^3x32"
+DEFAULT = "batch64-16^3x32"
 
 # point-sink workloads (determinant method): name -> nucleus, dims, seed workload id
 POINT_WORKLOADS = {
@@ -74,13 +77,17 @@ KINDS = {"2H": 4, "3He": 9, "3H": 9, "4He": 4}
 EROWS = {"2H": [4], "3He": [2, 2], "3H": [2, 2], "4He": [4]}
 
 
-def block_flops_per_site(nucleus):
-    """GEMM: 12 rows (i1) per kind x 144 columns x 3 E rows x 8 flops per complex
-    multiply-add; E rows: per nonzero diquark entry 6 complex products and
-    adds for the three colour cross products (8 flops each) per column."""
-    gemm = 12 * KINDS[nucleus] * 144 * 3 * 8
-    erow = sum(144 * npair * 6 * 8 for npair in EROWS[nucleus])
-    return gemm + erow
+def gemm_flops_per_site(nucleus, kinds=None):
+    """The MFMA contraction: 12 rows (i1) per kind x 144 columns x 3 E rows x 8
+    flops per complex multiply-add (counted as written, whatever the number of
+    real MFMAs a precision spends on one complex product)."""
+    return 12 * (KINDS[nucleus] if kinds is None else kinds) * 144 * 3 * 8
+
+
+def erow_flops_per_site(nucleus):
+    """The E rows on the vector ALU: per nonzero diquark entry 6 complex products
+    and adds for the three colour cross products (8 flops each) per column."""
+    return sum(144 * npair * 6 * 8 for npair in EROWS[nucleus])
 
 
 def kernel_source_hash():
@@ -113,7 +120,11 @@ def main():
     ap.add_argument("--workload", default=DEFAULT,
                     choices=sorted(WORKLOADS) + sorted(POINT_WORKLOADS) + sorted(GEVP_WORKLOADS))
     ap.add_argument("--precision", default=None, help="p64, p32, pb3, pb6 (default: the workload's)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--split", default=None,
+                    help="comma-separated split modes timed beside the main precision (default: p32,pb6 for "
+                         "batches, p32,pb3,pb6 for single correlators; 'none' for none)")
+    ap.add_argument("--samples", type=int, default=8, help="(correlator, time slice) pairs checked by the oracle")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip every oracle leg")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
     ap.add_argument("--no-truncation", action="store_true", help="skip the important-term truncation figures")
     ap.add_argument("--no-autotune", action="store_true",
@@ -150,6 +161,13 @@ def main():
     prec = args.precision or prec0
     X, Y, Z, T = dims
     V = X * Y * Z
+    single = len(items) == 1
+    if args.no_split or args.split == "none":
+        splits = []
+    elif args.split:
+        splits = [p for p in args.split.split(",") if p and p != prec]
+    else:
+        splits = [p for p in (("p32", "pb3", "pb6") if single else ("p32", "pb6")) if p != prec]
     dtype = np.complex128 if dts == "c128" else np.complex64
     t0 = time.time()
     hu, hd = gen_inputs(wid, n_cfg, dims, dtype)
@@ -165,18 +183,17 @@ def main():
         # launch shapes tuned on scratch inputs of this lattice (outside the timed region)
         t0 = time.time()
         for n in nuclei:
-            for p in ([prec] if len(items) > 1 or args.no_split else [prec, "p32", "pb3", "pb6"]):
+            for p in [prec] + splits:
                 W.autotune(plans[n], dims, dts, p)
         t_tune = time.time() - t0
         note(f"autotune {t_tune:.1f} s")
-    single = len(items) == 1
     if single:
         pl = plans[nuclei[0]]
         A, K, N = pl.info()
         B = torch.empty((n_cfg, T, K, W.BLOCK_LEN, 2), dtype=torch.float64, device="cuda")
         C = torch.empty((n_cfg, T, 2), dtype=torch.float64, device="cuda")
 
-        def step(p=prec):
+        def step(p, graph=True):
             W.blocks(pl, du, dd, p, out=B)
             W.contract(pl, B, out=C)
     else:
@@ -184,75 +201,46 @@ def main():
         bitems = [(nuclei.index(n), c) for n, c in items]
         C = torch.empty((len(items), T, 2), dtype=torch.float64, device="cuda")
 
-        def step(p=prec, graph=True):
+        def step(p, graph=True):
             W.correlator(plist, bitems, du, dd, p, use_graph=graph, out=C)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    W.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    W.profile(False)
-    kernels = ("blocks", "blocks_reduce", "contract", "contract_finalize")
-    prof = {k: W.profile_read(k) for k in kernels}
-    graph_ms = None
-    if not single:
-        # kernel events cannot sit inside the captured graph: the per-kernel
-        # durations come from the same batch launched eagerly
-        graph_ms = W.profile_read("correlator")
-        step(graph=False)
-        torch.cuda.synchronize()
-        W.profile(True)
-        for _ in range(args.steps):
-            step(graph=False)
-        torch.cuda.synchronize()
-        W.profile(False)
-        prof = {k: W.profile_read(k) for k in kernels}
-        eager = W.profile_read("correlator")
-        graph_ms = {"graph_launch_ms": graph_ms[1] / max(graph_ms[0], 1),
-                    "eager_batch_ms": eager[1] / max(eager[0], 1)}
+    runs = {}
+    for p in [prec] + splits:
+        runs[p] = timed_steps(W, torch, step, p, single, C, args.steps, args.warmup)
+        note(f"{p}: {runs[p]['ms_per_step']:.3f} ms/step")
 
-    note(f"timed {args.steps} steps: {1e3 * dt / args.steps:.3f} ms/step")
-    step_s = dt / args.steps
     n_term_evals = sum(plans[n].n_terms * T for n, _ in items)
-    flops_launch = sum(block_flops_per_site(n) * V * T for n, _ in items)
-    gemm_equiv = sum(165888.0 * plans[n].n_kinds * V * T for n, _ in items)
-    nb, ms_b = prof["blocks"]
-    avg_b = ms_b / max(nb, 1)
-    achieved_tf = flops_launch / (avg_b * 1e-3) / 1e12
-    nc, ms_c = prof["contract"]
-    avg_c = ms_c / max(nc, 1)
-    esz = 16 if dts == "c128" else 8
-    bytes_in = 2 * 144 * esz * V * T * len(items)
+    traffic = load_traffic(args.workload)
 
-    # HBM bytes per launch from rocprofv3 counters (profiles/traffic.json), valid
-    # only while the kernel sources are the ones the counters were taken on
-    traffic = {"blocks": None, "contract": None}
-    tfile = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tfile):
-        ent = json.load(open(tfile)).get(args.workload, {})
-        if ent.get("source_hash") == kernel_source_hash() and ent.get("precision") == prec:
-            for k in traffic:
-                traffic[k] = ent.get(k, {}).get("bytes_per_launch")
-    # term sum: 6A + 2 FP64 flops per term and time slice, FP64 vector ALU peak
-    # (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s)
-    sum_flops = sum(plans[n].n_terms * T * (6 * plans[n].A + 2) for n, _ in items)
-    sum_tf = sum_flops / (avg_c * 1e-3) / 1e12 if nc else 0.0
-    roof_blocks = {"bound": "mfma", "kernel": "blocks_nucleon_kernel", "achieved": achieved_tf,
-                   "peak": PEAK_TFLOPS[prec], "peak_name": PEAK_NAME[prec], "unit": "TFLOP/s",
-                   "frac": achieved_tf / PEAK_TFLOPS[prec], "traffic": traffic["blocks"],
-                   "flops_per_launch": flops_launch, "avg_launch_ms": avg_b}
-    roof_sum = {"bound": "alu", "kernel": "contract_tg_kernel" if single else "contract_batch_kernel",
-                "achieved": sum_tf, "peak": 78.6, "peak_name": "FP64 vector ALU", "unit": "TFLOP/s",
-                "frac": sum_tf / 78.6, "traffic": traffic["contract"], "flops_per_launch": sum_flops,
-                "avg_launch_ms": avg_c}
-    dominant = roof_blocks if avg_b >= avg_c else roof_sum
+    def rooflines(p, r):
+        prof = r["prof"]
+        nb, ms_b = prof["blocks"]
+        nc, ms_c = prof["contract"]
+        avg_b, avg_c = ms_b / max(nb, 1), ms_c / max(nc, 1)
+        gemm = sum(gemm_flops_per_site(n) * V * T for n, _ in items)
+        erow = sum(erow_flops_per_site(n) * V * T for n, _ in items)
+        tf_b = gemm / (avg_b * 1e-3) / 1e12
+        # term sum: 6A + 2 FP64 flops per term and time slice, FP64 vector ALU peak
+        # (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s)
+        sum_flops = sum(plans[n].n_terms * T * (6 * plans[n].A + 2) for n, _ in items)
+        tf_c = sum_flops / (avg_c * 1e-3) / 1e12 if nc else 0.0
+        tr = traffic.get(p, {})
+        rb = {"bound": "mfma", "kernel": "blocks_nucleon_kernel", "achieved": tf_b, "peak": PEAK_TFLOPS[p],
+              "peak_name": PEAK_NAME[p], "unit": "TFLOP/s", "frac": tf_b / PEAK_TFLOPS[p],
+              "traffic": tr.get("blocks"), "flops_per_launch": gemm, "avg_launch_ms": avg_b,
+              "erow_valu_flops_per_launch": erow, "erow_valu_tflops": erow / (avg_b * 1e-3) / 1e12}
+        if p in SPLIT_PRODUCTS:
+            # one BF16 MFMA pass per limb product: the mode's own effective peak
+            rb["frac_of_effective_peak"] = tf_b / (PEAK_TFLOPS[p] / SPLIT_PRODUCTS[p])
+        rc = {"bound": "alu", "kernel": "contract_tg_kernel" if single else "contract_batch_kernel",
+              "achieved": tf_c, "peak": 78.6, "peak_name": "FP64 vector ALU", "unit": "TFLOP/s",
+              "frac": tf_c / 78.6, "traffic": tr.get("contract"), "flops_per_launch": sum_flops,
+              "avg_launch_ms": avg_c}
+        return rb, rc
 
+    main_run = runs[prec]
+    rb, rc = rooflines(prec, main_run)
+    step_s = main_run["ms_per_step"] * 1e-3
     desc = ", ".join(f"{sum(1 for m, _ in items if m == n)}x {n}" for n in nuclei)
     out = {
         "metric": METRIC,
@@ -265,7 +253,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == "p64" else {"p32": "f32", "pb3": "bf16x3", "pb6": "bf16x6"}[prec],
+        "dtype": DTYPE_NAME[prec],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc} on {X}x{Y}x{Z}x{T}, {dts} propagators, {prec} blocks "
                                f"+ FP64 term sum, all {T} time slices, {n_cfg} configuration(s)"
@@ -273,28 +261,208 @@ def main():
                    "lattice": [X, Y, Z, T], "n_cfg": n_cfg, "storage": dts, "precision": prec,
                    "correlators": len(items), "nuclei": {n: {"A": plans[n].A, "kinds": plans[n].n_kinds,
                                                              "terms": plans[n].n_terms} for n in nuclei}},
-        "roofline": dominant,
-        "rooflines": {"blocks": roof_blocks, "term_sum": roof_sum},
+        "roofline": rb if rb["avg_launch_ms"] >= rc["avg_launch_ms"] else rc,
+        "rooflines": {"blocks": rb, "term_sum": rc},
         "blocks_per_s": sum(plans[n].n_kinds * T for n, _ in items) / step_s,
-        "block_tflops_gemm_equivalent": gemm_equiv / (avg_b * 1e-3) / 1e12,
-        "terms_per_s_contract_kernel": n_term_evals / (avg_c * 1e-3) if nc else None,
-        "kernel_ms": {k: (v[1] / v[0] if v[0] else None) for k, v in prof.items()},
-        "propagator_GBs_blocks_kernel": bytes_in / (avg_b * 1e-3) / 1e9,
-        "batch_timing": graph_ms,
+        "block_tflops": rb["achieved"],
+        "terms_per_s_contract_kernel": n_term_evals / (rc["avg_launch_ms"] * 1e-3) if rc["avg_launch_ms"] else None,
+        "kernel_ms": main_run["kernel_ms"],
+        "propagator_GBs_blocks_kernel": 2 * 144 * (16 if dts == "c128" else 8) * V * T * len(items)
+                                        / (rb["avg_launch_ms"] * 1e-3) / 1e9,
+        "batch_timing": main_run["graph"],
         "plan_s": t_plan,
         "autotune_s": t_tune if not args.no_autotune else None,
         "input_gen_s": t_gen,
     }
-    if single and prec == "p64" and not args.no_split:
-        out["split_precision"] = split_precision(W, pl, step, B, C, args.steps, flops_launch)
+    split_out = {}
+    for p in splits:
+        r = runs[p]
+        sb, sc = rooflines(p, r)
+        split_out[p] = {"ms_per_step": r["ms_per_step"], "wick_terms_per_s": n_term_evals / (r["ms_per_step"] * 1e-3),
+                        "speedup_vs_" + prec: main_run["ms_per_step"] / r["ms_per_step"],
+                        "dtype": DTYPE_NAME[p], "kernel_ms": r["kernel_ms"], "batch_timing": r["graph"],
+                        "rooflines": {"blocks": sb, "term_sum": sc},
+                        "roofline": sb if sb["avg_launch_ms"] >= sc["avg_launch_ms"] else sc}
+    if split_out:
+        out["split_precision"] = split_out
+    if not args.no_cpu_baseline:
+        note("oracle: sampled reference values and the cpu baseline")
+        samples = oracle_samples(items, plans, hu, hd, T, args.samples)
+        errs = {p: errors_vs_oracle(samples, runs[p]["C"], items, single, TOL[p]) for p in runs}
+        out["error_vs_oracle"] = {
+            "what": "|dC| / sum_n |term_n| (sum over the deduplicated table with the oracle's blocks) and "
+                    "|dC| / |C|, the oracle's C(t) from direct block sums and the subset-DP term sum",
+            "samples": [{"item": s["item"], "nucleus": s["nucleus"], "cfg": s["cfg"], "t": s["t"]} for s in samples],
+            **errs}
+        out["cpu_baseline"] = cpu_baseline(samples, plans)
+        if single and prec == "p64":
+            out["cpu_baseline"]["same_table"] = same_table_cpu(plans[items[0][0]])
     if single and not args.no_truncation:
         note("important-term truncation")
+        step(prec)
+        torch.cuda.synchronize()
         out["important_terms"] = important_terms(W, pl, B, C, args.steps, wid, dims, dts, prec,
                                                  not args.no_autotune)
-    if not args.no_cpu_baseline:
-        note("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(items, nuclei, hu, hd, plans, C.cpu().numpy())
     print(json.dumps(out))
+
+
+SPLIT_PRODUCTS = {"pb3": 3, "pb6": 6}
+DTYPE_NAME = {"p64": "f64", "p32": "f32", "pb3": "bf16x3", "pb6": "bf16x6"}
+# error bounds relative to sum_n |term_n|: FP64 blocks 1e-12, FP32 and three BF16
+# limbs 1e-8 (the split bound); two BF16 limbs are measured against 1e-6
+TOL = {"p64": 1e-12, "p32": 1e-8, "pb6": 1e-8, "pb3": 1e-6}
+KERNELS = ("blocks", "blocks_reduce", "contract", "contract_finalize")
+
+
+def timed_steps(W, torch, step, prec, single, C, steps, warmup):
+    """Warm up, then time `steps` steps between device synchronisations; the
+    per-kernel HIP-event durations come from the library's probes on the launch
+    stream. A graph-captured batch cannot hold the probes' events, so its
+    per-kernel durations come from the same batch launched eagerly afterwards."""
+    for _ in range(warmup):
+        step(prec)
+    torch.cuda.synchronize()
+    W.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(prec)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    W.profile(False)
+    Cg = C.cpu().numpy().copy()
+    prof = {k: W.profile_read(k) for k in KERNELS}
+    graph = None
+    if not single:
+        g = W.profile_read("correlator")
+        step(prec, graph=False)
+        torch.cuda.synchronize()
+        W.profile(True)
+        for _ in range(steps):
+            step(prec, graph=False)
+        torch.cuda.synchronize()
+        W.profile(False)
+        prof = {k: W.profile_read(k) for k in KERNELS}
+        e = W.profile_read("correlator")
+        graph = {"graph_launch_ms": g[1] / max(g[0], 1), "eager_batch_ms": e[1] / max(e[0], 1)}
+    return {"ms_per_step": 1e3 * dt, "C": Cg, "prof": prof, "graph": graph,
+            "kernel_ms": {k: (v[1] / v[0] if v[0] else None) for k, v in prof.items()}}
+
+
+def load_traffic(workload):
+    """HBM bytes per launch from rocprofv3 counters (profiles/traffic.json), per
+    precision, valid only while the kernel sources hash to the recorded value."""
+    out = {}
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(tfile):
+        return out
+    h = kernel_source_hash()
+    for key, ent in json.load(open(tfile)).items():
+        w, _, p = key.partition("|")
+        if w == workload and ent.get("source_hash") == h:
+            out[p] = {k: ent.get(k, {}).get("bytes_per_launch") for k in ("blocks", "contract")}
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def sample_pairs(items, T, n):
+    """(item, t) pairs for the oracle: the nuclei in proportion to their share of
+    the items, time slices spread over [0, T) and including the first and last."""
+    by_nuc = {}
+    for i, (nuc, _) in enumerate(items):
+        by_nuc.setdefault(nuc, []).append(i)
+    quota = {nuc: max(1, round(n * len(ix) / len(items))) for nuc, ix in by_nuc.items()}
+    ts = [0, T - 1] + [(5 + 7 * k) % T for k in range(n)]
+    out, k = [], 0
+    for nuc, ix in by_nuc.items():
+        for j in range(quota[nuc]):
+            out.append((ix[j % len(ix)], ts[k % len(ts)]))
+            k += 1
+    return out
+
+
+def compact_layout(B):
+    """[..., 12, 12, 12] antisymmetric blocks -> [..., 792], entry pair(i1 < i3) * 12 + i2
+    with pair(i1, i3) = i3 (i3 - 1) / 2 + i1 (the library's block layout)."""
+    out = np.zeros(B.shape[:-3] + (792,), dtype=B.dtype)
+    for i3 in range(12):
+        for i1 in range(i3):
+            out[..., (i3 * (i3 - 1) // 2 + i1) * 12:(i3 * (i3 - 1) // 2 + i1) * 12 + 12] = B[..., i1, :, i3]
+    return out
+
+
+def kind_order(op, pl):
+    """For each kind of the plan, the oracle operator's kind with the same flavors and weights."""
+    def canon(fl, w):
+        return tuple(int(f) for f in fl), tuple(sorted((int(a), int(b), int(c), int(x), int(y)) for a, b, c, x, y in w))
+    index = {}
+    for i, k in enumerate(op.kinds):
+        index.setdefault(canon(k.flavors, k.w), i)
+    return [index[canon(*pl.kind(k))] for k in range(pl.n_kinds)]
+
+
+def oracle_samples(items, plans, hu, hd, T, n):
+    """The oracle's C(t) (direct block sums, subset-DP term sum; timed) and the
+    error scale sum_n |term_n| (the plan's table with the oracle's blocks, Eq. 2.4
+    form) on sampled (item, time slice) pairs."""
+    import oracle
+    from oracle import operators as ops
+    tables = {}
+    out = []
+    for i, t in sample_pairs(items, T, n):
+        nuc, cfg = items[i]
+        op = ops.by_name(nuc)
+        su, sd = hu[cfg, t].astype(np.complex128), hd[cfg, t].astype(np.complex128)
+        t0 = time.perf_counter()
+        ref = op.scale * oracle.sum_dp(op, oracle.blocks_raw(op, su, sd))
+        dt = time.perf_counter() - t0
+        pl = plans[nuc]
+        if nuc not in tables:
+            kidx, coef = pl.table()
+            tables[nuc] = (kidx, np.abs(coef), kind_order(op, pl))
+        kidx, acoef, order = tables[nuc]
+        Bc = np.stack([compact_layout(oracle.block_eq24(op.kinds[k], su, sd)) for k in order])
+        mag = float(oracle.table_sum(kidx, acoef, np.abs(Bc).reshape(1, -1))[0].real)
+        out.append({"item": i, "nucleus": nuc, "cfg": cfg, "t": t, "C": ref, "mag": mag, "oracle_s": dt,
+                    "n_terms": pl.n_terms})
+    return out
+
+
+def errors_vs_oracle(samples, C, items, single, tol):
+    rel_terms, rel_c = [], []
+    for s in samples:
+        row = s["cfg"] if single else s["item"]
+        got = C[row, s["t"], 0] + 1j * C[row, s["t"], 1]
+        d = abs(got - s["C"])
+        rel_terms.append(d / s["mag"])
+        rel_c.append(d / max(abs(s["C"]), 1e-300))
+    return {"max_dC_over_sum_terms": float(max(rel_terms)), "max_dC_over_C": float(max(rel_c)),
+            "per_sample_dC_over_sum_terms": [float(v) for v in rel_terms],
+            "per_sample_dC_over_C": [float(v) for v in rel_c],
+            "bound": tol, "meets_bound": bool(max(rel_terms) <= tol)}
+
+
+def cpu_baseline(samples, plans):
+    """The oracle's own route (blocks by direct sums + subset-DP term sum) timed
+    on the sampled (item, time slice) pairs; value = table terms covered per second."""
+    import oracle
+    dt = sum(s["oracle_s"] for s in samples)
+    evals = sum(s["n_terms"] for s in samples)
+    which = ", ".join("%s cfg %d t %d" % (s["nucleus"], s["cfg"], s["t"]) for s in samples)
+    return {"value": evals / dt, "unit": "Wick terms/s", "cores": oracle.threads(), "cpu_model": cpu_model(),
+            "kind": "oracle",
+            "sample": f"{len(samples)} (nucleus, configuration, time slice) triples of the same workload "
+                      f"({which}): oracle blocks "
+                      f"(direct sums) + subset-DP term sum; value = deduplicated-table terms covered per second",
+            "seconds": dt}
 
 
 def gevp_bench(args):
@@ -351,7 +519,7 @@ def gevp_bench(args):
     nb, msb = prof["blocks"]
     nc, msc = prof["gevp_contract"]
     avg_b, avg_c = msb / max(nb, 1), msc / max(nc, 1)
-    flops_b = block_flops_per_site("2H") * info["n_kinds"] / KINDS["2H"] * V * T
+    flops_b = gemm_flops_per_site("2H", info["n_kinds"]) * V * T
     tf_b = flops_b / (avg_b * 1e-3) / 1e12
     E = n * n
     sum_flops = info["n_terms"] * T * (6 * (info["A"] - 1) + 4 * E)
@@ -382,8 +550,7 @@ def gevp_bench(args):
         note("cpu baseline (oracle, element by element)")
         import oracle
         from oracle import operators as ops
-        sys.path.insert(0, ROOT)
-        from tests.helpers import gevp_element
+        from oracle.operators import gevp_element
         op_list = [ops.deuteron(+1), ops.deuteron(-1), ops.deuteron(0)]
         t0 = time.perf_counter()
         done = 0
@@ -569,82 +736,6 @@ def important_terms(W, pl, B, C, steps, wid, dims, dts, prec, tune):
             "note": "synthetic propagators have no gauge structure, so the term values are not heavy-tailed "
                     "as in the paper's ensembles; the deviation shows the mechanics, not the physics",
             "fractions": res}
-
-
-def table_magnitude(pl, Bc):
-    """sum_n |coef_n prod_a B[kidx_{a,n}]| for blocks Bc [K, 792] (host, numpy)."""
-    kidx, coef = pl.table()
-    flat = Bc.reshape(-1)
-    prod = np.abs(coef)
-    for a in range(kidx.shape[0]):
-        prod = prod * np.abs(flat[kidx[a].astype(np.int64)])
-    return prod.sum()
-
-
-def split_precision(W, pl, step, B64, C64, steps, flops_launch):
-    """Each split mode timed like the FP64 step; its C(t) compared with the FP64
-    GPU result, relative to sum_n |term_n| (the table with the FP64 blocks)."""
-    import torch
-    step("p64")
-    torch.cuda.synchronize()
-    Bh = B64.cpu().numpy()
-    Bc = Bh[..., 0] + 1j * Bh[..., 1]
-    mag = np.array([[table_magnitude(pl, Bc[c, t]) for t in range(Bc.shape[1])] for c in range(Bc.shape[0])])
-    c64 = C64.cpu().numpy().copy()
-    res = {}
-    for prec in ("p32", "pb3", "pb6"):
-        step(prec)
-        torch.cuda.synchronize()
-        note(f"split precision {prec}")
-        W.profile(True)
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step(prec)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        W.profile(False)
-        nb, msb = W.profile_read("blocks")
-        cs = C64.cpu().numpy()
-        err = np.abs((cs[..., 0] - c64[..., 0]) + 1j * (cs[..., 1] - c64[..., 1])) / mag
-        avg = msb / max(nb, 1)
-        res[prec] = {"ms_per_step": 1e3 * dt / steps, "blocks_kernel_ms": avg,
-                     "block_tflops": flops_launch / (avg * 1e-3) / 1e12,
-                     "mfma_peak_frac": flops_launch / (avg * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
-                     "wick_terms_per_s": pl.n_terms * Bc.shape[0] * Bc.shape[1] / (dt / steps),
-                     "max_rel_err_vs_fp64": float(err.max()), "median_rel_err_vs_fp64": float(np.median(err)),
-                     "meets_1e-8": bool(err.max() <= 1e-8)}
-    step("p64")
-    torch.cuda.synchronize()
-    return res
-
-
-def cpu_baseline(items, nuclei, hu, hd, plans, C_gpu):
-    """The oracle (blocks + subset-DP term sum) on sampled (item, time slice) pairs."""
-    import oracle
-    from oracle import operators as ops
-    T = hu.shape[1]
-    done, diffs, evals = [], [], 0
-    t0 = time.perf_counter()
-    # (item, t) pairs in a fixed order until about 10 s of CPU work (or all of them)
-    order = [(i, (5 + 7 * k) % T) for k in range(T) for i in range(len(items))]
-    for i, t in order:
-        n, cfg = items[i]
-        op = ops.by_name(n)
-        Braw = oracle.blocks_raw(op, hu[cfg, t].astype(np.complex128), hd[cfg, t].astype(np.complex128))
-        c = op.scale * oracle.sum_dp(op, Braw)
-        got = C_gpu[i if len(items) > 1 else cfg, t, 0] + 1j * C_gpu[i if len(items) > 1 else cfg, t, 1]
-        diffs.append(abs(got - c) / max(abs(c), 1e-300))
-        done.append((n, cfg, t))
-        evals += plans[n].n_terms
-        if time.perf_counter() - t0 > 10.0:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": evals / dt, "unit": "Wick terms/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{len(done)} (nucleus, configuration, time slice) triples of the same workload, first "
-                      f"{done[:4]}: oracle blocks (direct sums) + subset-DP term sum; value = table terms "
-                      f"covered per second",
-            "seconds": dt, "gpu_vs_oracle_max_rel_diff_of_C": float(max(diffs)),
-            "same_table_numpy": same_table_cpu(plans[items[0][0]])}
 
 
 def same_table_cpu(pl):

@@ -42,10 +42,12 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle's C core with gcc (plain -O2, OpenMP)."""
+    """Compile the oracle's C core with gcc (-O3, OpenMP; no -ffast-math, so
+    every floating-point sum keeps its written order). Not -march=native: the
+    library is built on one host and may run on another."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
@@ -311,21 +313,6 @@ def point_correlator(op, Su, Sd, t_slices=None):
     return out
 
 
-def point_magnitude(op, Su, Sd, keys, coef, t_slices=None):
-    """Sum over sites of sum_n |merged term n| on the one-site blocks (the
-    error scale of a point-sink C(t)); keys, coef from merged_terms(op)."""
-    T = Su.shape[0]
-    ts = range(T) if t_slices is None else t_slices
-    out = np.zeros(len(ts))
-    for n, t in enumerate(ts):
-        su = _site_major(Su[t])
-        sd = _site_major(Sd[t])
-        for x in range(su.shape[0]):
-            B = np.stack([block_eq24(k, su[x:x + 1], sd[x:x + 1]) for k in op.kinds])[None]
-            out[n] += np.abs(term_values(keys, coef, B)).sum()
-    return out
-
-
 def point_det_magnitude(op, Su, Sd, t_slices=None):
     """Per time slice, sum over sites of sum_{g,h} |W_g W'_h det S_u[U_g; U'_h]
     det S_d[D_g; D'_h]|: the absolute terms of the determinant form of Eq. 2.9
@@ -366,7 +353,10 @@ def point_det_magnitude(op, Su, Sd, t_slices=None):
 
 def table_sum(kidx, coef, B_sets):
     """sum_n coef_n prod_a B[s].flat[kidx[a, n]] for every block set s, on all
-    threads (a given flat table evaluated on the CPU; for timing beside the GPU)."""
+    threads: a given flat term table (Eq. 2.6 written as a list of products of
+    block entries) evaluated on the CPU. With |coef| and |B| it gives
+    sum_n |term_n|, the error scale of a correlator; on the oracle's own merged
+    term list (``merged_terms``) it reproduces ``sum_dp``."""
     kidx = np.ascontiguousarray(kidx, dtype=np.uint16)
     coef = np.ascontiguousarray(coef, dtype=np.complex128)
     B = np.ascontiguousarray(B_sets, dtype=np.complex128).reshape(len(B_sets), -1)

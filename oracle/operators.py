@@ -184,6 +184,28 @@ def helium4():
     return Operator(4, kt.kinds, pats, list(pats), 1.0 / 96.0, "4He")
 
 
+def gevp_element(op_list, i, j):
+    """The (i, j) element of a correlation matrix (Eqs. E1-E3) as one Operator:
+    operator i at the sink, operator j at the source. The kinds are the union
+    of the operators' kinds (equal flavors and weights are one kind) and the
+    scale is sqrt(scale_i scale_j) (the paper gives no normalisation; each
+    scale is the square of an operator normalisation)."""
+    kinds, index, maps = [], {}, []
+    for op in op_list:
+        m = []
+        for k in op.kinds:
+            key = (tuple(k.flavors), tuple(sorted((a, b, c, x, y) for a, b, c, x, y in k.w if x or y)))
+            if key not in index:
+                index[key] = len(kinds)
+                kinds.append(k)
+            m.append(index[key])
+        maps.append(m)
+    snk = [(tuple(maps[i][k] for k in p), c) for p, c in op_list[i].snk]
+    src = [(tuple(maps[j][k] for k in p), c) for p, c in op_list[j].src]
+    scale = float(np.sqrt(op_list[i].scale * op_list[j].scale))
+    return Operator(op_list[i].A, kinds, snk, src, scale, f"{op_list[i].name}|{op_list[j].name}")
+
+
 def by_name(name):
     return {"2H": deuteron, "3He": helium3, "3H": triton, "4He": helium4}[name]()
 

@@ -764,9 +764,14 @@ struct BatchEntry {
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;  // for least-recently-used eviction
 };
 std::mutex g_batch_mu;
 std::map<std::string, BatchEntry> g_batch;
+uint64_t g_batch_clock = 0;
+// cached batches (work lists, workspaces, graph) kept at once; the least
+// recently used one is released when a new one would exceed this
+constexpr size_t kMaxBatchEntries = 8;
 thread_local bool t_capturing = false;
 
 void free_batch(BatchEntry &b)
@@ -1297,6 +1302,13 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
     std::lock_guard<std::mutex> lk(g_batch_mu);
     auto it = g_batch.find(key.str());
     if (it == g_batch.end()) {
+        while (g_batch.size() >= kMaxBatchEntries) {
+            auto lru = g_batch.begin();
+            for (auto jt = g_batch.begin(); jt != g_batch.end(); ++jt)
+                if (jt->second.last_use < lru->second.last_use) lru = jt;
+            free_batch(lru->second);  // waits for the device first
+            g_batch.erase(lru);
+        }
         BatchEntry b;
         const Tune tu = tune_for(plans[0], dims, (int)dtype, (int)prec);
         WICK_TRY(st = build_batch(plans, items, n_items, S_u, S_d, (int)dtype, dims, V, (int)prec,
@@ -1325,6 +1337,7 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
         }
         it = g_batch.emplace(key.str(), b).first;
     }
+    it->second.last_use = ++g_batch_clock;
     Probe pr("correlator", s);
     hipError_t e = it->second.exec ? hipGraphLaunch(it->second.exec, s) : launch_batch(it->second.L, s);
     pr.stop();

@@ -9,8 +9,9 @@
 // K = R per site summed over all sites. It runs on v_mfma_f64_16x16x4f64:
 // the A operand is E (lane l: column n = 16*tile + l%16, site l/16), the B
 // operand is Aop (lane l: site l/16, row m = 16*mtile + l%16 -> (kind, i1)),
-// so each MFMA contracts four sites at once. Complex products take four
-// real MFMAs (re*re - im*im, re*im + im*re).
+// so each MFMA contracts four sites at once. In this generic kernel a
+// complex product takes four real MFMAs (re*re - im*im, re*im + im*re); the
+// nucleon-form kernel below takes three in FP64 (Gauss's form).
 //
 // Sites are split into chunks (split-K); each wave writes its chunk's partial
 // block and a second kernel sums the chunks in a fixed order and
@@ -323,7 +324,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ void lds_dma16(const void *src, void *lds_dst)
 {
     const uint32_t l = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) void *)lds_dst;
-    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(l) : "memory");
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(l) : "memory", "m0");
 }
 
 typedef const __attribute__((address_space(4))) NucDesc CNucDesc;

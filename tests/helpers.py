@@ -6,6 +6,7 @@ import numpy as np
 
 import oracle
 from oracle import operators as ops
+from oracle.operators import gevp_element  # noqa: F401  (re-exported for the tests)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -97,27 +98,6 @@ def table_entries(op, pl):
 def row_index(keys):
     """{tuple(sorted row): position} for a [N, A] key array."""
     return {tuple(r): i for i, r in enumerate(np.sort(keys, axis=1).tolist())}
-
-
-def gevp_element(op_list, i, j):
-    """The (i, j) element of a correlation matrix as one oracle Operator: the
-    union of the operators' kinds (equal flavors and weights are one kind),
-    op i's sink patterns, op j's source patterns, scale sqrt(scale_i scale_j)."""
-    from oracle.operators import Operator
-    kinds, index, maps = [], {}, []
-    for op in op_list:
-        m = []
-        for k in op.kinds:
-            key = (tuple(k.flavors), tuple(sorted((a, b, c, x, y) for a, b, c, x, y in k.w if x or y)))
-            if key not in index:
-                index[key] = len(kinds)
-                kinds.append(k)
-            m.append(index[key])
-        maps.append(m)
-    snk = [(tuple(maps[i][k] for k in p), c) for p, c in op_list[i].snk]
-    src = [(tuple(maps[j][k] for k in p), c) for p, c in op_list[j].src]
-    scale = float(np.sqrt(op_list[i].scale * op_list[j].scale))
-    return Operator(op_list[i].A, kinds, snk, src, scale, f"{op_list[i].name}|{op_list[j].name}")
 
 
 def sorted_entries(ent):

@@ -20,8 +20,9 @@ def test_traffic_records_are_complete():
     path = os.path.join(ROOT, "profiles", "traffic.json")
     recs = json.load(open(path))
     assert recs
-    for workload, ent in recs.items():
-        assert ent["precision"] == "p64"
+    for key, ent in recs.items():
+        workload, _, prec = key.partition("|")
+        assert ent["precision"] == prec and prec in ("p64", "p32", "pb3", "pb6")
         assert len(ent["source_hash"]) == 16
         # copy calibration: FETCH_SIZE counts half the bytes read, WRITE_SIZE all written
         assert 1.9 < ent["fetch_factor"] < 2.1 and 0.95 < ent["write_factor"] < 1.05
@@ -31,6 +32,7 @@ def test_traffic_records_are_complete():
             assert e["bytes_per_launch"] > 0
             assert abs(e["fetch_bytes"] + e["write_bytes"] - e["bytes_per_launch"]) <= 1e-6 * e["bytes_per_launch"]
         # the block kernel reads both propagators at least once (4608 bytes per
-        # site and time slice of complex128)
-        dims = {"3He-16^3x32": 16 ** 3 * 32, "4He-24^3x48": 24 ** 3 * 48}[workload]
-        assert ent["blocks"]["fetch_bytes"] >= 0.99 * 4608 * dims
+        # site and time slice of complex128, 2304 of complex64)
+        sites, esz = {"3He-16^3x32": (16 ** 3 * 32, 4608), "4He-24^3x48": (24 ** 3 * 48, 4608),
+                      "batch64-16^3x32": (64 * 16 ** 3 * 32, 2304)}[workload]
+        assert ent["blocks"]["fetch_bytes"] >= 0.99 * esz * sites
