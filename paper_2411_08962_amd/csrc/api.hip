@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <deque>
 #include <cstdlib>
@@ -11,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <sstream>
 #include <string>
 #include <tuple>
@@ -123,6 +125,7 @@ struct DevPlan {
     int64_t *chunk_base = nullptr;
     int32_t *chunk_len = nullptr;
     int n_chunks = 0, seg_len = 0;
+    int coef_unit = 0;  // segmented table: integer-coefficient words when nonzero
 };
 
 TermTable table_of(const DevPlan *d, const wick_plan_s *p)
@@ -135,6 +138,7 @@ TermTable table_of(const DevPlan *d, const wick_plan_s *p)
     t.kidx = d->kidx;
     t.coef = d->coef;
     t.seg_prefix = d->seg_prefix;
+    t.coef_unit = d->coef_unit;
     t.chunk_base = d->chunk_base;
     t.chunk_len = d->chunk_len;
     t.n_chunks = d->n_chunks;
@@ -175,7 +179,76 @@ struct SegTable {
     std::vector<int32_t> len;
     std::vector<double2> pal;
     int seg_len = 0;
+    int32_t unit = 0;  // integer-coefficient words (see TermTable) when nonzero
 };
+
+// The common unit of a real table whose coefficients are integers: the gcd
+// g of their magnitudes when every coefficient is q * g with |q| <= the
+// word's limit, else 0 (the palette form is used).
+int32_t integer_unit(const wick_plan_s *p)
+{
+    const size_t nt = (size_t)p->n_terms;
+    uint64_t g = 0;
+    for (size_t n = 0; n < nt; ++n) {
+        const double re = p->coef_re[n];
+        if (p->coef_im[n] != 0.0 || re != std::floor(re) || std::fabs(re) >= 2147483648.0 || re == 0.0) return 0;
+        uint64_t a = (uint64_t)std::fabs(re), b = g;
+        while (b) { const uint64_t r = a % b; a = b; b = r; }
+        g = a;
+    }
+    if (g == 0 || g > ((uint64_t)1 << 20)) return 0;
+    for (size_t n = 0; n < nt; ++n)
+        if (std::fabs(p->coef_re[n]) / (double)g > kIntCoefMax) return 0;
+    return (int32_t)g;
+}
+
+// LDS bank balance of the gathers of integer-coefficient words. Step j of a
+// chunk gathers, for each lane, the node entry, leaf 0 and leaf 1 of the
+// lane's j-th word, as three wave-wide 16-byte LDS reads. A 16-byte entry e
+// lies in bank group e mod 16, and such a read takes longer the more lanes
+// of one half-wave hit the same group (measured on MI355X: about 1.45x from
+// random entries to at most two lanes per group). The sum of a segment does
+// not depend on the order of its words, so each lane's words are reordered
+// greedily: at each step the lanes of a half-wave in turn take, among their
+// next kBalanceWindow words, the one whose three groups are least used so
+// far at that step. Chunks are independent (host threads).
+constexpr int kBalanceWindow = 16;
+void balance_banks(SegTable &out, const std::vector<int32_t> &lane_len)
+{
+    const size_t n_chunks = out.base.size();
+    auto work = [&](size_t c_lo, size_t c_hi) {
+        for (size_t c = c_lo; c < c_hi; ++c) {
+            uint64_t *w = out.words.data() + out.base[c];
+            const int len = out.len[c];
+            const int32_t *ll = lane_len.data() + c * 64;
+            for (int j = 0; j < len; ++j)
+                for (int h = 0; h < 2; ++h) {
+                    uint8_t cnt[3][16] = {};
+                    for (int l = 32 * h; l < 32 * h + 32; ++l) {
+                        if (j >= ll[l]) continue;
+                        const int end = std::min(ll[l], j + kBalanceWindow);
+                        int best = j, best_cost = 1 << 30;
+                        for (int k = j; k < end; ++k) {
+                            const uint64_t v = w[(size_t)k * 64 + l];
+                            int cost = cnt[0][(v >> kPackBits) & 15] + cnt[1][v & 15];
+                            if (v >> 53) cost += cnt[2][(v >> (2 * kPackBits)) & 15];
+                            if (cost < best_cost) { best_cost = cost; best = k; }
+                        }
+                        std::swap(w[(size_t)j * 64 + l], w[(size_t)best * 64 + l]);
+                        const uint64_t v = w[(size_t)j * 64 + l];
+                        ++cnt[0][(v >> kPackBits) & 15];
+                        ++cnt[1][v & 15];
+                        if (v >> 53) ++cnt[2][(v >> (2 * kPackBits)) & 15];
+                    }
+                }
+        }
+    };
+    const size_t nth = std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
+    if (n_chunks < 64 || nth == 1) { work(0, n_chunks); return; }
+    std::vector<std::thread> th;
+    for (size_t i = 0; i < nth; ++i) th.emplace_back(work, n_chunks * i / nth, n_chunks * (i + 1) / nth);
+    for (auto &t : th) t.join();
+}
 
 bool segment_table(const wick_plan_s *p, SegTable &out)
 {
@@ -184,6 +257,12 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
     if (A < 2 || A > 4 || (int)p->kinds.size() > kMaxLdsKinds || nt == 0 || nt > 0xffffffffULL) return false;
     std::vector<uint8_t> pidx;
     if (!palette_of(p, true, pidx, out.pal)) return false;
+    const char *form_env = std::getenv("WICK_TABLE_FORM");
+    out.unit = form_env && std::string(form_env) == "segmented-palette" ? 0 : integer_unit(p);
+    auto qbits = [&](uint32_t t) {  // 11-bit two's complement of coef / unit
+        const int64_t q = (int64_t)(p->coef_re[t] / out.unit);
+        return (uint64_t)q & 0x7ff;
+    };
     const uint16_t *k = p->kidx.data();
     auto ix = [&](int a, uint32_t t) { return (uint32_t)k[(size_t)a * nt + t]; };
     // terms in lexicographic order of their index tuples (LSD radix sort, 14-bit digits)
@@ -248,15 +327,31 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
             for (uint32_t kk = 0; kk < nn; ++kk) {
                 const auto &nd = nodes[n0 + kk];
                 const uint32_t t0 = ord[nd.first];
-                uint64_t v = (uint64_t)ix(A - 1, t0) | ((uint64_t)ix(A - 2, t0) << kPackBits) |
-                             ((uint64_t)pidx[t0] << (2 * kPackBits));
-                if (nd.second > 1) {
-                    const uint32_t t1 = ord[nd.first + 1];
-                    v |= ((uint64_t)ix(A - 1, t1) << 36) | ((uint64_t)pidx[t1] << 50);
+                uint64_t v;
+                if (out.unit) {
+                    v = (uint64_t)ix(A - 1, t0) | ((uint64_t)ix(A - 2, t0) << kPackBits) | (qbits(t0) << 42);
+                    if (nd.second > 1) {
+                        const uint32_t t1 = ord[nd.first + 1];
+                        v |= ((uint64_t)ix(A - 1, t1) << 28) | (qbits(t1) << 53);
+                    }
+                } else {
+                    v = (uint64_t)ix(A - 1, t0) | ((uint64_t)ix(A - 2, t0) << kPackBits) |
+                        ((uint64_t)pidx[t0] << (2 * kPackBits));
+                    if (nd.second > 1) {
+                        const uint32_t t1 = ord[nd.first + 1];
+                        v |= ((uint64_t)ix(A - 1, t1) << 36) | ((uint64_t)pidx[t1] << 50);
+                    }
                 }
                 w[(size_t)kk * 64] = v;
             }
         }
+    if (out.unit && !std::getenv("WICK_NO_BANK_BALANCE")) {
+        // lengths of the lanes' segments, for the reordering below (the
+        // variable turns it off, for measurement)
+        std::vector<int32_t> lane_len(n_chunks * 64, 0);
+        for (size_t si = 0; si < segs.size(); ++si) lane_len[si] = (int32_t)segs[si].second;
+        balance_banks(out, lane_len);
+    }
     return true;
 }
 
@@ -489,13 +584,16 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
     const size_t nt = (size_t)p->n_terms;
     // table form: segmented for A >= 3 (sharing the leading indices pays:
     // 22 % faster than packed on 4He, 31 % on 3He), packed for A = 2, plain
-    // when neither fits; WICK_TABLE_FORM=plain|packed|segmented selects one (testing)
+    // when neither fits; WICK_TABLE_FORM=plain|packed|segmented|segmented-palette
+    // selects one (testing; segmented uses integer-coefficient words when the
+    // coefficients allow, segmented-palette never)
     const char *form_env = std::getenv("WICK_TABLE_FORM");
     const std::string form = form_env ? form_env : "";
     std::vector<uint64_t> words;
     std::vector<double2> pal;
     SegTable seg;
-    const bool segmented = (form == "segmented" || (form.empty() && p->A >= 3)) && segment_table(p, seg);
+    const bool segmented = (form == "segmented" || form == "segmented-palette" || (form.empty() && p->A >= 3)) &&
+                           segment_table(p, seg);
     const bool packed = !segmented && (form.empty() || form == "packed") && pack_table(p, words, pal);
     if (segmented) {
         words.swap(seg.words);
@@ -523,6 +621,7 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
     if (segmented) {
         d.n_chunks = (int)seg.base.size();
         d.seg_len = seg.seg_len;
+        d.coef_unit = seg.unit;
         if ((e = hipMemcpy(d.seg_prefix, seg.prefix.data(), seg.prefix.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemcpy(d.chunk_base, seg.base.data(), seg.base.size() * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemcpy(d.chunk_len, seg.len.data(), seg.len.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) {

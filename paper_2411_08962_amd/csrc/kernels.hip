@@ -324,7 +324,9 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ void lds_dma16(const void *src, void *lds_dst)
 {
     const uint32_t l = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) void *)lds_dst;
-    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(l) : "memory", "m0");
+    // the LDS address goes in through the M0 constraint: the compiler writes
+    // M0 itself and so keeps no value of its own there across this statement
+    asm volatile("global_load_lds_dwordx4 %0, off" : : "v"(src), "{m0}"(l) : "memory");
 }
 
 typedef const __attribute__((address_space(4))) NucDesc CNucDesc;
@@ -922,6 +924,91 @@ __device__ __forceinline__ void term_sum_seg(const double2 *__restrict__ sB, int
     }
 }
 
+// Term sum over the chunks [c0, c1) of a segmented table with
+// integer-coefficient words, for NTG staged slices (a compile-time count, so
+// that the gathers of every slice are issued together and one wait covers
+// them). A missing leaf (q = 0) and a padding word read entry 0 and weigh it
+// by zero; lanes reading one address share the read.
+template <int A, int NTG>
+__device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, int KB, const TermTable &tab, int c0,
+                                              int c1, double (&ar)[kMaxTG], double (&ai)[kMaxTG])
+{
+    constexpr uint32_t kMask = (1u << kPackBits) - 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int unit = tab.coef_unit;
+    for (int c = c0 + wave; c < c1; c += kCThreads / 64) {
+        const uint32_t pre = tab.seg_prefix[(int64_t)c * 64 + lane];
+        double sx[NTG], sy[NTG];
+#pragma unroll
+        for (int tg = 0; tg < NTG; ++tg) sx[tg] = sy[tg] = 0.0;
+        const uint64_t *wp = tab.words + tab.chunk_base[c] + lane;
+        const int nodes = tab.chunk_len[c];  // uniform over the wave
+        auto eval = [&](uint64_t w) {
+            const int l0 = (int)(w & kMask), in = (int)((w >> kPackBits) & kMask);
+            const int l1 = (int)((w >> (2 * kPackBits)) & kMask);
+            const double cf0 = (double)((int)((int64_t)(w << 11) >> 53) * unit);
+            const double cf1 = (double)((int)((int64_t)w >> 53) * unit);
+            double2 b0[NTG], b1[NTG], bn[NTG];
+#pragma unroll
+            for (int tg = 0; tg < NTG; ++tg) {
+                const double2 *Bt = sB + tg * KB;
+                bn[tg] = Bt[in];
+                b0[tg] = Bt[l0];
+                b1[tg] = Bt[l1];
+            }
+#pragma unroll
+            for (int tg = 0; tg < NTG; ++tg) {
+                const double s3x = fma(cf1, b1[tg].x, cf0 * b0[tg].x);
+                const double s3y = fma(cf1, b1[tg].y, cf0 * b0[tg].y);
+                sx[tg] += bn[tg].x * s3x - bn[tg].y * s3y;
+                sy[tg] += bn[tg].x * s3y + bn[tg].y * s3x;
+            }
+        };
+        // the words of the next kPrefetch nodes are loaded while the current
+        // ones are evaluated (indices clamped into the chunk: always valid)
+        uint64_t cur[kPrefetch], nxt[kPrefetch];
+        auto fetch = [&](int k0, uint64_t (&w)[kPrefetch]) {
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) w[u] = wp[(int64_t)(k0 + u < nodes ? k0 + u : nodes - 1) * 64];
+        };
+        if (nodes > 0) fetch(0, cur);
+        for (int k0 = 0; k0 < nodes; k0 += kPrefetch) {
+            if (k0 + kPrefetch < nodes) fetch(k0 + kPrefetch, nxt);
+            if (k0 + kPrefetch <= nodes) {
+#pragma unroll
+                for (int u = 0; u < kPrefetch; ++u) eval(cur[u]);
+            } else {
+                for (int u = 0; u < nodes - k0; ++u) eval(cur[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) cur[u] = nxt[u];
+        }
+#pragma unroll
+        for (int tg = 0; tg < NTG; ++tg) {
+            double px = 1.0, py = 0.0;
+#pragma unroll
+            for (int a = 0; a < A - 2; ++a) {
+                const double2 b = sB[tg * KB + ((pre >> (kPackBits * a)) & kMask)];
+                const double x = px * b.x - py * b.y;
+                py = px * b.y + py * b.x;
+                px = x;
+            }
+            ar[tg] += px * sx[tg] - py * sy[tg];
+            ai[tg] += px * sy[tg] + py * sx[tg];
+        }
+    }
+}
+
+template <int A>
+__device__ __forceinline__ void term_sum_segi_n(const double2 *__restrict__ sB, int KB, int ntg, const TermTable &tab,
+                                                int c0, int c1, double (&ar)[kMaxTG], double (&ai)[kMaxTG])
+{
+    static_assert(kMaxTG == 3, "one instance per slice count");
+    if (ntg == 3) term_sum_segi<A, 3>(sB, KB, tab, c0, c1, ar, ai);
+    else if (ntg == 2) term_sum_segi<A, 2>(sB, KB, tab, c0, c1, ar, ai);
+    else term_sum_segi<A, 1>(sB, KB, tab, c0, c1, ar, ai);
+}
+
 // Stage ntg slices of K blocks (contiguous in B) and the palette.
 __device__ __forceinline__ void stage_blocks(const double2 *__restrict__ Bsrc, int n, const TermTable &tab,
                                              double2 *__restrict__ sB, double2 *__restrict__ spal)
@@ -968,7 +1055,7 @@ __device__ __forceinline__ void reduce_tg(double (&ar)[kMaxTG], double (&ai)[kMa
 // One plan: workgroup (group of tg consecutive (cfg, t) sets, table slice);
 // a slice is slice_len terms (plain, packed) or slice_len chunks (segmented).
 // FORM: 0 plain, 1 packed, 2 segmented, 3 packed with a real palette,
-// 4 segmented with a real palette.
+// 4 segmented with a real palette, 5 segmented with integer coefficients.
 template <int A, int FORM>
 __global__ __launch_bounds__(kCThreads) void contract_tg_kernel(const double2 *__restrict__ B, TermTable tab,
                                                                 int64_t N, int K, int n_ct, int tg, int n_slices,
@@ -988,10 +1075,11 @@ __global__ __launch_bounds__(kCThreads) void contract_tg_kernel(const double2 *_
     double2 *spal = lds, *sB = lds + kMaxPalette;
     stage_blocks(B + (int64_t)ct0 * KB, ntg * KB, tab, sB, spal);
     double ar[kMaxTG] = {}, ai[kMaxTG] = {};
-    if constexpr (FORM == 2 || FORM == 4) {
+    if constexpr (FORM == 2 || FORM == 4 || FORM == 5) {
         const int c0 = (int)(slice * slice_len);
         const int c1 = c0 + slice_len < tab.n_chunks ? (int)(c0 + slice_len) : tab.n_chunks;
-        term_sum_seg<A, FORM == 4>(sB, KB, ntg, spal, tab, c0, c1, ar, ai);
+        if constexpr (FORM == 5) term_sum_segi_n<A>(sB, KB, ntg, tab, c0, c1, ar, ai);
+        else term_sum_seg<A, FORM == 4>(sB, KB, ntg, spal, tab, c0, c1, ar, ai);
     } else {
         const int64_t n0 = (int64_t)slice * slice_len;
         const int64_t n1 = n0 + slice_len < N ? n0 + slice_len : N;
@@ -1078,7 +1166,10 @@ __global__ __launch_bounds__(kCThreads) void contract_batch_kernel(const double2
     if (it.tab.seg_prefix) {
         const int c0 = (int)(w.slice * it.slice_len);
         const int c1 = c0 + it.slice_len < it.tab.n_chunks ? (int)(c0 + it.slice_len) : it.tab.n_chunks;
-        switch (it.A * 2 + (it.tab.coef_real ? 1 : 0)) {
+        switch (it.tab.coef_unit ? 10 + it.A : it.A * 2 + (it.tab.coef_real ? 1 : 0)) {
+        case 12: term_sum_segi_n<2>(sB, KB, ntg, it.tab, c0, c1, ar, ai); break;
+        case 13: term_sum_segi_n<3>(sB, KB, ntg, it.tab, c0, c1, ar, ai); break;
+        case 14: term_sum_segi_n<4>(sB, KB, ntg, it.tab, c0, c1, ar, ai); break;
         case 4: term_sum_seg<2, false>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
         case 5: term_sum_seg<2, true>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
         case 6: term_sum_seg<3, false>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
@@ -1246,28 +1337,32 @@ hipError_t launch_contract(const ContractLaunch &L, hipStream_t s)
         if (L.tg > kMaxTG || L.tg * L.K > kMaxLdsKinds) return hipErrorInvalidValue;
         const int64_t n_groups = (L.n_ct + L.tg - 1) / L.tg;
         const unsigned blocks = (unsigned)round8(n_groups * L.n_slices);
-        const int form = L.tab.seg_prefix ? (L.tab.coef_real ? 4 : 2) : (L.tab.words ? (L.tab.coef_real ? 3 : 1) : 0);
+        const int form = L.tab.seg_prefix ? (L.tab.coef_unit ? 5 : (L.tab.coef_real ? 4 : 2))
+                                           : (L.tab.words ? (L.tab.coef_real ? 3 : 1) : 0);
         hipError_t e = hipErrorInvalidValue;
-        switch (L.A * 5 + form) {
-        case 5: e = launch_tg<1, 0>(L, s, blocks); break;
-        case 6: e = launch_tg<1, 1>(L, s, blocks); break;
-        case 8: e = launch_tg<1, 3>(L, s, blocks); break;
-        case 10: e = launch_tg<2, 0>(L, s, blocks); break;
-        case 11: e = launch_tg<2, 1>(L, s, blocks); break;
-        case 12: e = launch_tg<2, 2>(L, s, blocks); break;
-        case 13: e = launch_tg<2, 3>(L, s, blocks); break;
-        case 14: e = launch_tg<2, 4>(L, s, blocks); break;
-        case 15: e = launch_tg<3, 0>(L, s, blocks); break;
-        case 16: e = launch_tg<3, 1>(L, s, blocks); break;
-        case 17: e = launch_tg<3, 2>(L, s, blocks); break;
-        case 18: e = launch_tg<3, 3>(L, s, blocks); break;
-        case 19: e = launch_tg<3, 4>(L, s, blocks); break;
-        case 20: e = launch_tg<4, 0>(L, s, blocks); break;
-        case 21: e = launch_tg<4, 1>(L, s, blocks); break;
-        case 22: e = launch_tg<4, 2>(L, s, blocks); break;
-        case 23: e = launch_tg<4, 3>(L, s, blocks); break;
-        case 24: e = launch_tg<4, 4>(L, s, blocks); break;
-        case 25: e = launch_tg<5, 0>(L, s, blocks); break;
+        switch (L.A * 8 + form) {
+        case 8: e = launch_tg<1, 0>(L, s, blocks); break;
+        case 9: e = launch_tg<1, 1>(L, s, blocks); break;
+        case 11: e = launch_tg<1, 3>(L, s, blocks); break;
+        case 16: e = launch_tg<2, 0>(L, s, blocks); break;
+        case 17: e = launch_tg<2, 1>(L, s, blocks); break;
+        case 18: e = launch_tg<2, 2>(L, s, blocks); break;
+        case 19: e = launch_tg<2, 3>(L, s, blocks); break;
+        case 20: e = launch_tg<2, 4>(L, s, blocks); break;
+        case 21: e = launch_tg<2, 5>(L, s, blocks); break;
+        case 24: e = launch_tg<3, 0>(L, s, blocks); break;
+        case 25: e = launch_tg<3, 1>(L, s, blocks); break;
+        case 26: e = launch_tg<3, 2>(L, s, blocks); break;
+        case 27: e = launch_tg<3, 3>(L, s, blocks); break;
+        case 28: e = launch_tg<3, 4>(L, s, blocks); break;
+        case 29: e = launch_tg<3, 5>(L, s, blocks); break;
+        case 32: e = launch_tg<4, 0>(L, s, blocks); break;
+        case 33: e = launch_tg<4, 1>(L, s, blocks); break;
+        case 34: e = launch_tg<4, 2>(L, s, blocks); break;
+        case 35: e = launch_tg<4, 3>(L, s, blocks); break;
+        case 36: e = launch_tg<4, 4>(L, s, blocks); break;
+        case 37: e = launch_tg<4, 5>(L, s, blocks); break;
+        case 40: e = launch_tg<5, 0>(L, s, blocks); break;
         default: break;
         }
         if (e != hipSuccess) return e;

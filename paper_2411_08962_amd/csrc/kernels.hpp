@@ -97,7 +97,16 @@ constexpr int kMaxPalette = 256;
 // word bits: leaf 0 [0,14), node index [14,28), palette index of leaf 0
 // [28,36), leaf 1 [36,50), palette index of leaf 1 [50,58); palette entry 0
 // is zero.
+//
+// Integer-coefficient words (coef_unit != 0: every coefficient is a real
+// integer multiple q * coef_unit with |q| <= 1023, true of every built-in
+// nucleus): leaf 0 [0,14), node index [14,28), leaf 1 [28,42), q of leaf 0
+// [42,53) and q of leaf 1 [53,64), both two's complement. The coefficient
+// is formed in registers (q * coef_unit is an exact integer), so no palette
+// is read from LDS; q = 0 marks a missing leaf (its gather is skipped), and
+// a word with q of leaf 0 equal to 0 is padding (no gather at all).
 constexpr int kNodeLeaves = 2;
+constexpr int kIntCoefMax = 1023;
 struct TermTable {
     const uint64_t *words;  // packed [N] or segmented (interleaved chunks), or null
     const double2 *pal;     // packed / segmented: palette [n_pal]
@@ -110,6 +119,7 @@ struct TermTable {
     const int64_t *chunk_base;   // [n_chunks]
     const int32_t *chunk_len;    // [n_chunks]
     int32_t n_chunks;
+    int32_t coef_unit;           // segmented form: 0 palette words, else integer-coefficient words
 };
 
 // The term sum stages the blocks of up to kMaxTG consecutive time slices of

@@ -289,7 +289,7 @@ def test_autotune_cache_and_parity(tmp_path, name, dims, prec):
 
 
 # ------------------------------------------------------------- table forms
-@pytest.mark.parametrize("form", ["plain", "packed", "segmented"])
+@pytest.mark.parametrize("form", ["plain", "packed", "segmented", "segmented-palette"])
 @pytest.mark.parametrize("name,dims", [("2H", (3, 2, 2, 3)), ("3He", (3, 1, 1, 2)), ("3H", (2, 2, 1, 4))])
 def test_term_table_forms(monkeypatch, form, name, dims):
     """Every device form of the term table (plain indices, packed words,
