@@ -197,6 +197,23 @@ wick_status wick_blocks(wick_plan_t plan, const void *S_u, const void *S_d, wick
 wick_status wick_contract(wick_plan_t plan, const double *B, int32_t n_cfg, int32_t T,
                           wick_stream_t stream, double *C);
 
+/* wick_contract for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and launch shape, so C is bitwise equal to wick_contract's,
+ * but the partial sums go to a static device array of 131072 complex FP64
+ * entries (2 MiB) that the library holds on each GPU until the process ends,
+ * and nothing is allocated (no hipMalloc / hipFree, no profiling events).
+ * Preconditions: the plan's table is already on the current device (one
+ * wick_contract or wick_blocks call with this plan on this device, made
+ * beforehand, puts it there; else WICK_EINVAL). A launch that needs more
+ * than 131072 partial sums (n_cfg * T * table slices) is WICK_ETOOBIG. Every
+ * call on one GPU uses that GPU's single array: calls that overlap on one
+ * GPU (several streams or threads) race and give wrong C; serialise them.
+ * Each call writes every partial sum it reads, so nothing needs clearing.
+ * Asynchronous on stream; the caller owns B and C. */
+wick_status wick_contract_noalloc(wick_plan_t plan, const double *B, int32_t n_cfg, int32_t T,
+                                  wick_stream_t stream, double *C);
+
 /* Both steps for a batch of (plan, configuration) items, which may mix
  * nuclei: C is device double [n_items][T][2]. use_graph = 1 captures the
  * launches in a hipGraph on first use of this (plans, items, dims, prec)

@@ -778,13 +778,36 @@ wick_status do_blocks(wick_plan_s *p, const void *Su, const void *Sd, int dtype,
     return WICK_OK;
 }
 
+// The device copy of a plan on the current device, without building it:
+// WICK_EINVAL when it is not there yet (no allocation of any kind).
+wick_status resident_plan(wick_plan_s *p, DevPlan **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev.find(p);
+    if (it != g_dev.end())
+        for (auto &d : it->second)
+            if (d.device == dev) {
+                *out = &d;
+                return WICK_OK;
+            }
+    return fail(WICK_EINVAL, "the plan's table is not on this device yet: call wick_contract (or wick_blocks) "
+                             "with it once on this device first");
+}
+
+// The term sum. With `fixed` set, the partial sums go to fixed[0 .. cap)
+// (bytes) instead of the stream's workspace, the plan must already be on the
+// device, and nothing is allocated; a launch needing more than cap bytes of
+// partial sums is WICK_ETOOBIG.
 wick_status do_contract(wick_plan_s *p, const double *B, int n_cfg, int T, hipStream_t s, double *C,
-                        int64_t slice_override = 0)
+                        int64_t slice_override = 0, void *fixed = nullptr, size_t cap = 0)
 {
     if (!B || !C) return fail(WICK_EINVAL, "wick_contract: null pointer");
     if (n_cfg < 1 || T < 1) return fail(WICK_EINVAL, "wick_contract: n_cfg and T must be >= 1");
     DevPlan *dp;
-    wick_status st = device_plan(p, s, &dp);
+    wick_status st = fixed ? resident_plan(p, &dp) : device_plan(p, s, &dp);
     if (st != WICK_OK) return st;
     const int64_t n_ct = (int64_t)n_cfg * T;
     if (p->n_terms == 0) {
@@ -811,7 +834,15 @@ wick_status do_contract(wick_plan_s *p, const double *B, int n_cfg, int T, hipSt
     }
     if ((int64_t)L.n_slices * n_groups > 0x7ffffff0LL) return fail(WICK_ETOOBIG, "wick_contract: grid too large");
     void *ws;
-    if ((st = workspace(s, (size_t)n_ct * L.n_slices * 16, &ws)) != WICK_OK) return st;
+    const size_t bytes = (size_t)n_ct * L.n_slices * 16;
+    if (fixed) {
+        if (bytes > cap)
+            return fail(WICK_ETOOBIG, "wick_contract_noalloc: " + std::to_string(n_ct * L.n_slices) +
+                                          " partial sums exceed the static scratch of " + std::to_string(cap / 16));
+        ws = fixed;
+    } else if ((st = workspace(s, bytes, &ws)) != WICK_OK) {
+        return st;
+    }
     L.partial = (double *)ws;
     L.C = C;
     hipError_t e = launch_contract(L, s);
@@ -872,6 +903,7 @@ uint64_t g_batch_clock = 0;
 // recently used one is released when a new one would exceed this
 constexpr size_t kMaxBatchEntries = 8;
 thread_local bool t_capturing = false;
+thread_local bool t_no_alloc = false;  // inside wick_contract_noalloc: no profiling events
 
 void free_batch(BatchEntry &b)
 {
@@ -1213,7 +1245,7 @@ wick_status autotune(wick_plan_s *p, const int32_t dims[4], int dtype, int prec,
 Probe::Probe(const char *n, hipStream_t st) : name(n), s(st)
 {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof_on || t_capturing) return;
+    if (!g_prof_on || t_capturing || t_no_alloc) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
     (void)hipEventRecord(a, s);
 }
@@ -1270,6 +1302,36 @@ using namespace wick;
     } catch (...) {                                                 \
         return fail(WICK_EINVAL, "internal error");                 \
     }
+
+// ------------------------------------------- allocation-free term sum
+// The partial sums of wick_contract_noalloc live in this static device array
+// (one copy per GPU, kept until the process ends). Host code never uses its
+// name as an address: the device address of each GPU's copy is looked up
+// once per device with hipGetSymbolAddress and used from then on.
+namespace {
+constexpr size_t kScratchPartials = 131072;  // complex FP64 partial sums: 2 MiB
+__device__ __align__(256) double2 scratch[kScratchPartials];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+wick_status noalloc_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(WICK_EUNSUPPORTED, "wick_contract_noalloc: device index");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return WICK_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -1369,6 +1431,23 @@ wick_status wick_contract(wick_plan_t p, const double *B, int32_t n_cfg, int32_t
 {
     if (!p) return fail(WICK_EINVAL, "wick_contract: null plan");
     WICK_TRY(return do_contract(p, B, n_cfg, T, (hipStream_t)stream, C));
+}
+
+wick_status wick_contract_noalloc(wick_plan_t p, const double *B, int32_t n_cfg, int32_t T, wick_stream_t stream,
+                                  double *C)
+{
+    if (!p) return fail(WICK_EINVAL, "wick_contract_noalloc: null plan");
+    void *ptr = nullptr;
+    wick_status st = noalloc_scratch(&ptr);
+    if (st != WICK_OK) return st;
+    t_no_alloc = true;
+    try {
+        st = do_contract(p, B, n_cfg, T, (hipStream_t)stream, C, 0, ptr, kScratchPartials * sizeof(double2));
+    } catch (...) {
+        st = fail(WICK_EINVAL, "wick_contract_noalloc: internal error");
+    }
+    t_no_alloc = false;
+    return st;
 }
 
 wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wick_item *items, int32_t n_items,

@@ -53,7 +53,7 @@ EXPORTS = ["wick_plan", "wick_plan_std", "wick_plan_info", "wick_plan_stats", "w
            "wick_version", "wick_profile", "wick_profile_read", "wick_point_plan", "wick_point_plan_std",
            "wick_point_info", "wick_point_correlator", "wick_point_destroy", "wick_gevp_plan", "wick_gevp_info",
            "wick_gevp_table", "wick_gevp_kinds", "wick_gevp_contract", "wick_gevp_destroy", "wick_gevp_plan_std",
-           "wick_plan_std_pair", "wick_point_blocks_correlator"]
+           "wick_plan_std_pair", "wick_point_blocks_correlator", "wick_contract_noalloc"]
 
 _lib = None
 
@@ -83,6 +83,7 @@ def lib():
     L.wick_plan_destroy.restype = None
     L.wick_blocks.argtypes = [P, P, P, st, P, i32, st, P, P]
     L.wick_contract.argtypes = [P, P, i32, i32, P, P]
+    L.wick_contract_noalloc.argtypes = [P, P, i32, i32, P, P]
     L.wick_correlator.argtypes = [P, i32, P, i32, P, P, st, P, i32, st, i32, P, P]
     L.wick_autotune.argtypes = [P, P, st, st, ctypes.c_char_p]
     L.wick_shutdown.argtypes = []
@@ -463,6 +464,21 @@ def contract(p: Plan, B, out=None):
     _check_out(out, (n_cfg, T, 2), B.device)
     _check(lib().wick_contract(p.handle, ctypes.c_void_p(B.data_ptr()), n_cfg, T, _stream(),
                                ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def contract_noalloc(p: Plan, B, out):
+    """wick_contract_noalloc: as contract(), into a caller-provided out
+    [n_cfg, T, 2] float64; the library allocates nothing (see wick.h)."""
+    torch = _torch()
+    if not B.is_cuda or not B.is_contiguous() or B.dtype != torch.float64 or B.dim() != 5:
+        raise ValueError("B must be a contiguous float64 device tensor [n_cfg, T, K, 792, 2]")
+    n_cfg, T = B.shape[:2]
+    if B.shape[2:] != (p.n_kinds, BLOCK_LEN, 2):
+        raise ValueError("B does not match the plan's kinds")
+    _check_out(out, (n_cfg, T, 2), B.device)
+    _check(lib().wick_contract_noalloc(p.handle, ctypes.c_void_p(B.data_ptr()), n_cfg, T, _stream(),
+                                       ctypes.c_void_p(out.data_ptr())))
     return out
 
 
