@@ -53,18 +53,26 @@ def reference(name, hu, hd, cfg, t):
 
 
 def test_helium4_24cubed_x48_per_t_error():
-    """4He on 24^3 x 48 (complex128): FP64, FP32 and two-limb BF16 blocks, each
-    followed by the FP64 term sum; per-time-slice error on sampled slices."""
+    """4He on 24^3 x 48 (complex128): FP64, FP32, two-limb and three-limb BF16
+    blocks, each followed by the FP64 term sum; per-time-slice error against
+    the oracle on eight slices spanning the lattice (first and last included):
+    |dC| / sum|terms| is asserted, |dC| / |C| is printed beside it."""
     import paper_2411_08962_amd as w
     pl = plan("4He")
     hu, hd, du, dd = props(3, 1, (24, 24, 24, 48))
-    Cs = {p: w.contract(pl, w.blocks(pl, du, dd, p)).cpu().numpy() for p in ("p64", "p32", "pb3")}
-    for t in (0, 23, 47):
+    precs = ("p64", "p32", "pb3", "pb6")
+    Cs = {p: w.contract(pl, w.blocks(pl, du, dd, p)).cpu().numpy() for p in precs}
+    print("\n  t  " + "  ".join(f"{p}: dC/sum|terms|  dC/|C|  " for p in precs), flush=True)
+    for t in (0, 7, 13, 20, 27, 34, 41, 47):
         ref, mag = reference("4He", hu, hd, 0, t)
+        row, bad = [], []
         for p, C in Cs.items():
-            rel = abs(C[0, t, 0] + 1j * C[0, t, 1] - ref) / mag
-            print(f"4He t={t} {p}: |dC|/sum|terms| = {rel:.3e}", flush=True)
-            assert rel <= TOL[p], (p, t, rel)
+            d = abs(C[0, t, 0] + 1j * C[0, t, 1] - ref)
+            row.append(f"{d / mag:9.2e} {d / abs(ref):9.2e}")
+            if d / mag > TOL[p]:
+                bad.append((p, t, d / mag))
+        print(f" {t:2d}  " + "    ".join(row), flush=True)
+        assert not bad, bad
 
 
 def test_lithium7_clusters_32cubed_x64():
