@@ -237,6 +237,22 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
 wick_status wick_autotune(wick_plan_t plan, const int32_t dims[4], wick_dtype dtype,
                           wick_precision prec, const char *cache_path);
 
+/* Tune a batched launch as a whole (wick_correlator with these plans, item
+ * tables, dims, dtype and precision): the block kernel's sites per
+ * workgroup and the term sum's terms per workgroup, each picked by timing
+ * eager launches of the whole batch on the caller's propagators S_u, S_d
+ * (device, as for wick_correlator; read only). Blocking; it uses a stream of
+ * its own and a C buffer it allocates and frees. The choice is kept under a
+ * key of (dims, dtype, prec, multiset of the items' tables) and used by every
+ * later wick_correlator call with that key (a batch already cached by
+ * wick_correlator keeps its shape); with a cache_path it is merged into that
+ * text file as for wick_autotune. Errors as for wick_correlator and
+ * wick_autotune. */
+wick_status wick_autotune_batch(const wick_plan_t *plans, int32_t n_plans, const wick_item *items,
+                                int32_t n_items, const void *S_u, const void *S_d, wick_dtype dtype,
+                                const int32_t dims[4], int32_t n_cfg, wick_precision prec,
+                                const char *cache_path);
+
 /* ------------------------------------------------- correlation matrices */
 
 /* Correlation matrix for the generalized eigenvalue problem (Eqs. E1-E3):

@@ -690,6 +690,38 @@ int64_t tuned_slice(const wick_plan_s *p, int64_t n_ct)
     return it == g_slice.end() ? 0 : it->second;
 }
 
+// batched launches tuned as a whole: (block sites per workgroup, terms per
+// term-sum workgroup), keyed by the lattice, storage, precision and the
+// multiset of the items' tables (which configuration an item reads does not
+// change the launch)
+std::map<std::string, std::pair<int, int64_t>> g_batch_tune;
+
+std::string batch_key(const wick_plan_t *plans, const wick_item *items, int n_items, const int32_t dims[4], int dtype,
+                      int prec)
+{
+    std::map<std::string, int> count;
+    for (int i = 0; i < n_items; ++i) {
+        const wick_plan_s *p = plans[items[i].plan];
+        std::ostringstream o;
+        o << "A" << p->A << "K" << p->kinds.size() << "N" << p->n_terms;
+        ++count[o.str()];
+    }
+    std::ostringstream o;
+    o << "gfx950:" << dims[0] << "x" << dims[1] << "x" << dims[2] << "x" << dims[3] << ":d" << dtype << ":p" << prec;
+    for (auto &kv : count) o << ":" << kv.first << "x" << kv.second;
+    return o.str();
+}
+
+bool tuned_batch(const std::string &key, int *chunk, int64_t *terms)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_batch_tune.find(key);
+    if (it == g_batch_tune.end()) return false;
+    *chunk = it->second.first;
+    *terms = it->second.second;
+    return true;
+}
+
 // terms per workgroup: about 1024 workgroups over all n_groups (sets of time
 // slices), at least 4096 terms each, a multiple of the workgroup size
 int64_t default_slice_len(int64_t N, int64_t n_groups)
@@ -931,7 +963,7 @@ template <class T> wick_status upload(const std::vector<T> &h, T **d)
 
 wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_items, const void *S_u,
                         const void *S_d, int dtype, const int32_t dims[4], int64_t V, int prec, int chunk_hint,
-                        double *C, BatchEntry &b)
+                        double *C, BatchEntry &b, int64_t terms_hint = 0)
 {
     const int T = dims[3];
     (void)hipGetDevice(&b.device);
@@ -972,7 +1004,8 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
     }
     // and at most 2^20 terms per workgroup (measured on the 64-configuration batch:
     // 2^20 is 10 % faster than 2^23 and 20 % faster than the uncapped 2^24.4)
-    int64_t S = std::max<int64_t>(4096, std::min<int64_t>((total + 2047) / 2048, 1 << 20));
+    int64_t S = terms_hint > 0 ? terms_hint
+                               : std::max<int64_t>(4096, std::min<int64_t>((total + 2047) / 2048, 1 << 20));
     S = (S + kCThreads - 1) / kCThreads * kCThreads;
     for (int i = 0; i < n_items; ++i) {
         wick_plan_s *p = plans[items[i].plan];
@@ -1062,6 +1095,7 @@ wick_status load_tune_file(const char *path)
         return fail(WICK_ECORRUPT, std::string("tune cache ") + path + ": bad header");
     std::map<std::string, Tune> tb;
     std::map<std::string, int64_t> ts;
+    std::map<std::string, std::pair<int, int64_t>> tbt;
     int ln = 1;
     while (std::getline(f, line)) {
         ++ln;
@@ -1074,6 +1108,11 @@ wick_status load_tune_file(const char *path)
             ok = static_cast<bool>(is >> t.chunk_sites >> t.batch_chunk_sites) && t.chunk_sites >= 4 &&
                  t.chunk_sites <= (1 << 24) && t.batch_chunk_sites >= 0 && t.batch_chunk_sites <= (1 << 24);
             if (ok) tb[key] = t;
+        } else if (ok && what == "batch") {
+            int c = 0;
+            int64_t v = 0;
+            ok = static_cast<bool>(is >> c >> v) && c >= 4 && c <= (1 << 24) && v >= 1024 && v <= (1LL << 30);
+            if (ok) tbt[key] = {c, v};
         } else if (ok && what == "contract") {
             int64_t v = 0;
             ok = static_cast<bool>(is >> v) && v >= 1 && v <= (1LL << 30);  // terms or chunks per workgroup
@@ -1087,6 +1126,7 @@ wick_status load_tune_file(const char *path)
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto &kv : tb) g_tune[kv.first] = kv.second;
     for (auto &kv : ts) g_slice[kv.first] = kv.second;
+    for (auto &kv : tbt) g_batch_tune[kv.first] = kv.second;
     return WICK_OK;
 }
 
@@ -1101,6 +1141,8 @@ wick_status save_tune_file(const char *path)
         for (auto &kv : g_tune) f << "blocks " << kv.first << ' ' << kv.second.chunk_sites << ' '
                                   << kv.second.batch_chunk_sites << "\n";
         for (auto &kv : g_slice) f << "contract " << kv.first << ' ' << kv.second << "\n";
+        for (auto &kv : g_batch_tune)
+            f << "batch " << kv.first << ' ' << kv.second.first << ' ' << kv.second.second << "\n";
         if (!f) return fail(WICK_EINVAL, std::string("cannot write tune cache ") + tmp);
     }
     if (std::rename(tmp.c_str(), path) != 0) return fail(WICK_EINVAL, std::string("cannot replace ") + path);
@@ -1237,6 +1279,83 @@ wick_status autotune(wick_plan_s *p, const int32_t dims[4], int dtype, int prec,
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[key] = Tune{best_chunk, best_batch};
         if (best_slice > 0) g_slice[skey] = best_slice;
+    }
+    return cache_path ? save_tune_file(cache_path) : WICK_OK;
+}
+
+// Arguments of a batched call (wick_correlator, wick_autotune_batch).
+wick_status check_batch(const wick_plan_t *plans, int n_plans, const wick_item *items, int n_items, const void *S_u,
+                        const void *S_d, int dtype, const int32_t dims[4], int n_cfg, int prec, int64_t *V)
+{
+    if (!plans || n_plans < 1 || !items || n_items < 1 || !S_u || !S_d)
+        return fail(WICK_EINVAL, "batch: bad plans / items / pointers");
+    if (((uintptr_t)S_u | (uintptr_t)S_d) & 15) return fail(WICK_EINVAL, "batch: propagators must be 16-byte aligned");
+    wick_status st = check_dims(dims, n_cfg, V);
+    if (st != WICK_OK) return st;
+    if (dtype != WICK_C128 && dtype != WICK_C64) return fail(WICK_EINVAL, "batch: bad dtype");
+    if (prec < WICK_P64 || prec > WICK_PB6) return fail(WICK_EINVAL, "batch: bad precision");
+    for (int i = 0; i < n_plans; ++i)
+        if (!plans[i]) return fail(WICK_EINVAL, "batch: null plan");
+    for (int i = 0; i < n_items; ++i)
+        if (items[i].plan < 0 || items[i].plan >= n_plans || items[i].cfg < 0 || items[i].cfg >= n_cfg)
+            return fail(WICK_EINVAL, "batch: item index out of range");
+    return WICK_OK;
+}
+
+// A batched launch tuned as a whole on the caller's propagators: the block
+// kernel's sites per workgroup (one site chunk per (item, t) down to
+// sixteen), then the term sum's terms per workgroup (2^16 .. 2^22), each by
+// timing eager launches of the whole batch (blocking, on a stream of its own).
+wick_status autotune_batch(const wick_plan_t *plans, int n_plans, const wick_item *items, int n_items,
+                           const void *S_u, const void *S_d, int dtype, const int32_t dims[4], int n_cfg, int prec,
+                           const char *cache_path)
+{
+    int64_t V;
+    wick_status st = check_batch(plans, n_plans, items, n_items, S_u, S_d, dtype, dims, n_cfg, prec, &V);
+    if (st != WICK_OK) return st;
+    if (cache_path && (st = load_tune_file(cache_path)) != WICK_OK) return st;
+    const std::string key = batch_key(plans, items, n_items, dims, dtype, prec);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (g_batch_tune.count(key)) return WICK_OK;
+    }
+    TuneScratch sc;
+    hipError_t e;
+    if ((e = hipMalloc(&sc.C, (size_t)n_items * dims[3] * 16)) != hipSuccess)
+        return fail(WICK_ENOMEM, std::string("wick_autotune_batch hipMalloc: ") + hipGetErrorString(e));
+    if ((e = hipStreamCreateWithFlags(&sc.s, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "wick_autotune_batch stream");
+    auto run = [&](int chunk, int64_t terms, float *ms) {
+        BatchEntry b;
+        wick_status r = build_batch(plans, items, n_items, S_u, S_d, dtype, dims, V, prec, chunk, (double *)sc.C, b,
+                                    terms);
+        if (r == WICK_OK)
+            r = time_runs(sc.s, 2, [&] {
+                hipError_t le = launch_batch(b.L, sc.s);
+                return le == hipSuccess ? WICK_OK : hip_fail(le, "wick_autotune_batch launch");
+            }, ms);
+        free_batch(b);
+        return r;
+    };
+    int best_chunk = 0;
+    float best = 0.f;
+    for (int div = 1; div <= 16; div *= 2) {
+        const int c = (int)((V + div - 1) / div + 7) / 8 * 8;
+        if (div > 1 && c < 256) break;
+        float ms = 0.f;
+        if ((st = run(c, 0, &ms)) != WICK_OK) return st;
+        if (!best_chunk || ms < best) { best = ms; best_chunk = c; }
+    }
+    int64_t best_terms = 0;
+    best = 0.f;
+    for (int64_t S = 1 << 16; S <= (1 << 22); S *= 2) {
+        float ms = 0.f;
+        if ((st = run(best_chunk, S, &ms)) != WICK_OK) return st;
+        if (!best_terms || ms < best) { best = ms; best_terms = S; }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_batch_tune[key] = {best_chunk, best_terms};
     }
     return cache_path ? save_tune_file(cache_path) : WICK_OK;
 }
@@ -1454,20 +1573,10 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
                             const void *S_u, const void *S_d, wick_dtype dtype, const int32_t dims[4], int32_t n_cfg,
                             wick_precision prec, int32_t use_graph, wick_stream_t stream, double *C)
 {
-    if (!plans || n_plans < 1 || !items || n_items < 1 || !C || !S_u || !S_d)
-        return fail(WICK_EINVAL, "wick_correlator: bad plans / items / pointers");
-    if (((uintptr_t)S_u | (uintptr_t)S_d) & 15)
-        return fail(WICK_EINVAL, "wick_correlator: propagators must be 16-byte aligned");
+    if (!C) return fail(WICK_EINVAL, "wick_correlator: null output");
     int64_t V;
-    wick_status st = check_dims(dims, n_cfg, &V);
+    wick_status st = check_batch(plans, n_plans, items, n_items, S_u, S_d, (int)dtype, dims, n_cfg, (int)prec, &V);
     if (st != WICK_OK) return st;
-    if (dtype != WICK_C128 && dtype != WICK_C64) return fail(WICK_EINVAL, "wick_correlator: bad dtype");
-    if (prec < WICK_P64 || prec > WICK_PB6) return fail(WICK_EINVAL, "wick_correlator: bad precision");
-    for (int i = 0; i < n_plans; ++i)
-        if (!plans[i]) return fail(WICK_EINVAL, "wick_correlator: null plan");
-    for (int i = 0; i < n_items; ++i)
-        if (items[i].plan < 0 || items[i].plan >= n_plans || items[i].cfg < 0 || items[i].cfg >= n_cfg)
-            return fail(WICK_EINVAL, "wick_correlator: item index out of range");
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -1488,9 +1597,13 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
             g_batch.erase(lru);
         }
         BatchEntry b;
-        const Tune tu = tune_for(plans[0], dims, (int)dtype, (int)prec);
-        WICK_TRY(st = build_batch(plans, items, n_items, S_u, S_d, (int)dtype, dims, V, (int)prec,
-                                  tu.batch_chunk_sites, C, b));
+        // launch shape: tuned for this batch (wick_autotune_batch), else the
+        // first plan's batched block shape and the default term split
+        int chunk = tune_for(plans[0], dims, (int)dtype, (int)prec).batch_chunk_sites;
+        int64_t terms = 0;
+        (void)tuned_batch(batch_key(plans, items, n_items, dims, (int)dtype, (int)prec), &chunk, &terms);
+        WICK_TRY(st = build_batch(plans, items, n_items, S_u, S_d, (int)dtype, dims, V, (int)prec, chunk, C, b,
+                                  terms));
         if (st != WICK_OK) {
             free_batch(b);
             return st;
@@ -1528,6 +1641,14 @@ wick_status wick_autotune(wick_plan_t p, const int32_t dims[4], wick_dtype dtype
 {
     if (!p) return fail(WICK_EINVAL, "wick_autotune: null plan");
     WICK_TRY(return autotune(p, dims, (int)dtype, (int)prec, cache_path));
+}
+
+wick_status wick_autotune_batch(const wick_plan_t *plans, int32_t n_plans, const wick_item *items, int32_t n_items,
+                                const void *S_u, const void *S_d, wick_dtype dtype, const int32_t dims[4],
+                                int32_t n_cfg, wick_precision prec, const char *cache_path)
+{
+    WICK_TRY(return autotune_batch(plans, n_plans, items, n_items, S_u, S_d, (int)dtype, dims, n_cfg, (int)prec,
+                                   cache_path));
 }
 
 wick_status wick_shutdown(void)

@@ -298,21 +298,23 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_f64_staged_kernel(
 //        (Gauss): with E = a + ib and Aop = c + id, K1 += (a + b) c,
 //        K2 += a (d - c), K3 += b (c + d), then Re = K1 - K3, Im = K1 + K2,
 //        formed once per workgroup after the site loop;
-//   P32: v_mfma_f32_16x16x4f32 with E and Aop rounded to FP32;
+//   P32: v_mfma_f32_16x16x4f32, the same three products with E, the sums
+//        a + b and d - c, c + d rounded to FP32 (complex64 entries are used
+//        as they are stored);
 //   PB3: v_mfma_f32_16x16x32_bf16, E and Aop split into two BF16 limbs
 //        (hi + lo), the three products hi*hi + hi*lo + lo*hi packed along K:
 //        one MFMA per real/imaginary output;
 //   PB6: three limbs (hi + mid + lo) and the six products of limb order <= 2:
 //        two MFMAs per output.
-// In the split modes the operands are scaled by exact powers of two (2^-2e
-// for E, 2^-e for Aop, e the exponent of the largest propagator entry of the
-// chunk's first batch), the MFMAs accumulate in FP32 for one batch of kSB
-// sites only, and each batch is folded into FP64 accumulators with the exact
-// factor 2^3e. Operand layout of the BF16 MFMA (measured): A[i][k] at lane
+// In the split modes E is scaled by an exact power of two per wave and group
+// (see the kernel) and Aop is not scaled; the MFMAs accumulate in FP32 over
+// a few batches and are folded into FP64 accumulators with the exact inverse
+// factor. Operand layout of the BF16 MFMA (measured): A[i][k] at lane
 // i + 16*(k/8), element k%8; B[k][j] at lane j + 16*(k/8); D as for the f32
 // 16x16x4 MFMA, row 4*(lane/16) + item, column lane%16. Lane group q
 // (= k/8 for BF16, = k for the 16x16x4 MFMAs) is site q of the step.
 typedef float f4 __attribute__((ext_vector_type(4)));
+extern "C" __device__ int __ockl_wfred_max_i32(int);  // wave-wide maximum (device library)
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // One wave-wide 16-byte-per-lane load from global memory straight into LDS:
@@ -361,7 +363,6 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
     // compiler can tell the reads of one from the loads into the other
     __shared__ __attribute__((aligned(16))) TIn sbuf0[2][kNucSites][144];
     __shared__ __attribute__((aligned(16))) TIn sbuf1[2][kNucSites][144];
-    __shared__ double smax[kNucWaves];
     const int lbw = xcd_block();
     if (lbw >= n_work * kNucColGroups) return;
     // the kNucColGroups workgroups of one work unit are adjacent (one XCD, shared L2)
@@ -465,33 +466,44 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
     issue(0, &sbuf0[0][0][0]);
     wait_staged();
     __syncthreads();
-    // split modes: operand scales 2^-2e (E) and 2^-e (Aop), from the first batch
-    double scE = 1.0, scA = 1.0, unscale = 1.0;
-    if constexpr (kSplit) {
-        double mx = 0.0;
-        for (int e = threadIdx.x; e < kEntries; e += kNucThreads) {
-            const double2 v = rd(&sbuf0[0][0][0] + e);
-            mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
-        }
+    // Split modes: the MFMAs of a group accumulate FP32 sums of E' * Aop with
+    // E' = E * 2^-sc and Aop unscaled (a propagator entry is an FP32 number or
+    // close to one). sc, the group's current scale, is the exponent of the
+    // largest |E| of the wave (wave-uniform, so every MFMA sum has one scale);
+    // it changes only when a batch's largest |E| moves more than kScaleSlack
+    // binades away, and the FP32 sums are folded into the FP64 accumulators
+    // with the exact factor 2^sc then, every kFoldBatches batches and at the
+    // end. |E'| stays within 2^+-kScaleSlack of the wave's largest entry, so no
+    // product leaves the FP32 range for any propagator magnitude.
+    constexpr int kNoScale = -100000, kScaleSlack = 24, kFoldBatches = 4, kExpBias = 2048;
+    f4 acc32[NT][3];  // P32: Gauss products K1, K2, K3; BF16 modes: Re, Im
+    int sc[NT];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-        if (lane == 0) smax[wv] = mx;
-        __syncthreads();
-        mx = 0.0;
-#pragma unroll
-        for (int w = 0; w < kNucWaves; ++w) mx = fmax(mx, smax[w]);
-        const int e = mx > 0.0 ? ilogb(mx) : 0;
-        scA = ldexp(1.0, -e);
-        scE = ldexp(1.0, -2 * e);
-        unscale = ldexp(1.0, 3 * e);
+    for (int t = 0; t < NT; ++t) {
+        acc32[t][0] = acc32[t][1] = acc32[t][2] = f4{0, 0, 0, 0};
+        sc[t] = kNoScale;
     }
+    int nfold = 0;
+    // split modes: acc (FP64, (Re, Im)) += 2^sc * this tile's FP32 sums
+    auto fold = [&](int t) {
+        if constexpr (kSplit) {
+            const double u = ldexp(1.0, sc[t]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if constexpr (MODE == WICK_P32) {
+                    const double k1 = acc32[t][0][v], k2 = acc32[t][1][v], k3 = acc32[t][2][v];
+                    acc[t][0][v] = fma(k1 - k3, u, acc[t][0][v]);
+                    acc[t][1][v] = fma(k1 + k2, u, acc[t][1][v]);
+                } else {
+                    acc[t][0][v] = fma((double)acc32[t][0][v], u, acc[t][0][v]);
+                    acc[t][1][v] = fma((double)acc32[t][1][v], u, acc[t][1][v]);
+                }
+            }
+            acc32[t][0] = acc32[t][1] = acc32[t][2] = f4{0, 0, 0, 0};
+        }
+    };
     // one staged batch: this wave's site quad against every group of the pass
     auto batch = [&](const TIn (*buf)[kNucSites][144]) {
-        f4 acc32[NT][2];
-        if constexpr (kSplit) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc32[t][0] = acc32[t][1] = f4{0, 0, 0, 0};
-        }
         {
             const int s = 4 * ph + q;   // this wave's site quad; sites past the end are zeros in LDS: E = 0
 #pragma unroll 1
@@ -535,6 +547,32 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
                     for (; p < G.npos + G.nneg; ++p) cross(p, -1.0, 1.0);
                     for (; p < G.npair; ++p) cross(p, 1.0, (double)G.m[p]);
                 }
+                double fE = 1.0;  // split modes: E' = E * 2^-sc of this group
+                if constexpr (kSplit) {
+                    const double m = fmax(fmax(fmax(fabs(e0x), fabs(e0y)), fmax(fabs(e1x), fabs(e1y))),
+                                          fmax(fabs(e2x), fabs(e2y)));
+                    const int bw = __ockl_wfred_max_i32(m > 0.0 ? ilogb(m) + kExpBias : 0);
+                    int cur = kNoScale;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        if (tgroup[t] == g) cur = sc[t];
+                    int want = cur;
+                    if (bw != 0) {
+                        const int x = min(max(bw - kExpBias, -1000), 1000);
+                        if (cur == kNoScale || x > cur + kScaleSlack || x < cur - kScaleSlack) want = x;
+                    } else if (cur == kNoScale) {
+                        want = 0;  // every E of the group is zero so far: any scale
+                    }
+                    if (want != cur) {
+#pragma unroll
+                        for (int t = 0; t < NT; ++t)
+                            if (tgroup[t] == g) {
+                                if (cur != kNoScale) fold(t);
+                                sc[t] = want;
+                            }
+                    }
+                    fE = ldexp(1.0, -want);
+                }
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     const double ex = r == 0 ? e0x : (r == 1 ? e1x : e2x);
@@ -554,31 +592,36 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
                             acc3[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey, v[t].x + v[t].y, acc3[t], 0, 0, 0);
                         }
                     } else if constexpr (MODE == WICK_P32) {
-                        const float fx = (float)(ex * scE), fy = (float)(ey * scE);
-                        // every tile's entry first (a tile of another group reads
-                        // offset 0, inside the buffer), then the MFMAs
-                        float2 v[NT];
+                        // Gauss's three products in FP32: K1 += (a + b) c,
+                        // K2 += a (d - c), K3 += b (c + d) with E' = a + ib and
+                        // the S_f entry c + id (Re = K1 - K3, Im = K1 + K2 at the fold)
+                        const double exs = ex * fE, eys = ey * fE;
+                        const float fab = (float)(exs + eys), fa = (float)exs, fb = (float)eys;
+                        float vc[NT], vdc[NT], vcd[NT];
 #pragma unroll
                         for (int t = 0; t < NT; ++t) {
-                            const double2 d = rd(sfb + (tgroup[t] == g ? bo[t] : 0) + 12 * r);
-                            v[t] = float2{(float)(d.x * scA), (float)(d.y * scA)};
+                            const TIn e = sfb[(tgroup[t] == g ? bo[t] : 0) + 12 * r];
+                            if constexpr (sizeof(TIn) == 8) {
+                                vc[t] = e.x;
+                                vdc[t] = e.y - e.x;
+                                vcd[t] = e.x + e.y;
+                            } else {
+                                vc[t] = (float)e.x;
+                                vdc[t] = (float)(e.y - e.x);
+                                vcd[t] = (float)(e.x + e.y);
+                            }
                         }
 #pragma unroll
                         for (int t = 0; t < NT; ++t) {
                             if (tgroup[t] != g) continue;
-                            acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fx, v[t].x, acc32[t][0], 0, 0, 0);
-                            acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fx, v[t].y, acc32[t][1], 0, 0, 0);
-                        }
-#pragma unroll
-                        for (int t = 0; t < NT; ++t) {
-                            if (tgroup[t] != g) continue;
-                            acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(-fy, v[t].y, acc32[t][0], 0, 0, 0);
-                            acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fy, v[t].x, acc32[t][1], 0, 0, 0);
+                            acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fab, vc[t], acc32[t][0], 0, 0, 0);
+                            acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, vdc[t], acc32[t][1], 0, 0, 0);
+                            acc32[t][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb, vcd[t], acc32[t][2], 0, 0, 0);
                         }
                     } else if constexpr (MODE == WICK_PB3) {
                         __bf16 xh, xl, yh, yl;
-                        split2(ex * scE, xh, xl);
-                        split2(ey * scE, yh, yl);
+                        split2(ex * fE, xh, xl);
+                        split2(ey * fE, yh, yl);
                         const __bf16 z = (__bf16)0.0f;
                         const bf8 Aop = bf8{xh, xh, xl, yh, yh, yl, z, z};
 #pragma unroll
@@ -586,8 +629,8 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
                             if (tgroup[t] != g) continue;
                             const double2 d = rd(sfb + bo[t] + 12 * r);
                             __bf16 axh, axl, ayh, ayl;
-                            split2(d.x * scA, axh, axl);
-                            split2(d.y * scA, ayh, ayl);
+                            split2(d.x, axh, axl);
+                            split2(d.y, ayh, ayl);
                             const bf8 Bre = bf8{axh, axl, axh, -ayh, -ayl, -ayh, z, z};
                             const bf8 Bim = bf8{ayh, ayl, ayh, axh, axl, axh, z, z};
                             acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop, Bre, acc32[t][0], 0, 0, 0);
@@ -595,8 +638,8 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
                         }
                     } else {
                         __bf16 xh, xm, xl, yh, ym, yl;
-                        split3(ex * scE, xh, xm, xl);
-                        split3(ey * scE, yh, ym, yl);
+                        split3(ex * fE, xh, xm, xl);
+                        split3(ey * fE, yh, ym, yl);
                         const __bf16 z = (__bf16)0.0f;
                         const bf8 Ax = bf8{xh, xh, xm, xh, xm, xl, z, z};
                         const bf8 Ay = bf8{yh, yh, ym, yh, ym, yl, z, z};
@@ -605,8 +648,8 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
                             if (tgroup[t] != g) continue;
                             const double2 d = rd(sfb + bo[t] + 12 * r);
                             __bf16 ah, am, al, bh, bm, bl;
-                            split3(d.x * scA, ah, am, al);
-                            split3(d.y * scA, bh, bm, bl);
+                            split3(d.x, ah, am, al);
+                            split3(d.y, bh, bm, bl);
                             const bf8 Bx = bf8{ah, am, ah, al, am, ah, z, z};
                             const bf8 By = bf8{bh, bm, bh, bl, bm, bh, z, z};
                             const bf8 nBy = bf8{-bh, -bm, -bh, -bl, -bm, -bh, z, z};
@@ -620,14 +663,12 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
             }
         }
         if constexpr (kSplit) {
-            // fold this batch's FP32 sums into the FP64 accumulators (exact rescale)
+            if (++nfold == kFoldBatches) {
+                nfold = 0;
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    acc[t][0][v] += (double)acc32[t][0][v] * unscale;
-                    acc[t][1][v] += (double)acc32[t][1][v] * unscale;
-                }
+                for (int t = 0; t < NT; ++t)
+                    if (sc[t] != kNoScale) fold(t);
+            }
         }
     };
     for (int b = 0; b < nb; b += 2) {
@@ -640,6 +681,11 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
         batch(sbuf1);
         wait_staged();
         __syncthreads();
+    }
+    if constexpr (kSplit) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            if (sc[t] != kNoScale) fold(t);
     }
     if constexpr (MODE == WICK_P64) {
         // (K1, K2, K3) -> (Re, Im) = (K1 - K3, K1 + K2)

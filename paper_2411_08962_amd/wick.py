@@ -53,7 +53,8 @@ EXPORTS = ["wick_plan", "wick_plan_std", "wick_plan_info", "wick_plan_stats", "w
            "wick_version", "wick_profile", "wick_profile_read", "wick_point_plan", "wick_point_plan_std",
            "wick_point_info", "wick_point_correlator", "wick_point_destroy", "wick_gevp_plan", "wick_gevp_info",
            "wick_gevp_table", "wick_gevp_kinds", "wick_gevp_contract", "wick_gevp_destroy", "wick_gevp_plan_std",
-           "wick_plan_std_pair", "wick_point_blocks_correlator", "wick_contract_noalloc"]
+           "wick_plan_std_pair", "wick_point_blocks_correlator", "wick_contract_noalloc",
+           "wick_autotune_batch"]
 
 _lib = None
 
@@ -86,6 +87,7 @@ def lib():
     L.wick_contract_noalloc.argtypes = [P, P, i32, i32, P, P]
     L.wick_correlator.argtypes = [P, i32, P, i32, P, P, st, P, i32, st, i32, P, P]
     L.wick_autotune.argtypes = [P, P, st, st, ctypes.c_char_p]
+    L.wick_autotune_batch.argtypes = [P, i32, P, i32, P, P, st, P, i32, st, ctypes.c_char_p]
     L.wick_shutdown.argtypes = []
     L.wick_profile.argtypes = [i32]
     L.wick_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
@@ -528,6 +530,19 @@ def autotune(p: Plan, dims, dtype="c128", precision="p64", cache_path=None):
     d = (ctypes.c_int32 * 4)(*dims)
     _check(lib().wick_autotune(p.handle, d, C128 if dtype == "c128" else C64, PRECISIONS[precision],
                                None if cache_path is None else str(cache_path).encode()))
+
+
+def autotune_batch(plans, items, S_u, S_d, precision="p64", cache_path=None):
+    """Tune the batched launch of correlator(plans, items, S_u, S_d, precision)
+    as a whole (block sites and term-sum terms per workgroup)."""
+    n_cfg, T, dims, dtype = _prop_args(S_u, S_d)
+    hp = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    it = (_Item * len(items))()
+    for i, (pi, cfg) in enumerate(items):
+        it[i].plan, it[i].cfg = int(pi), int(cfg)
+    _check(lib().wick_autotune_batch(hp, len(plans), it, len(items), ctypes.c_void_p(S_u.data_ptr()),
+                                     ctypes.c_void_p(S_d.data_ptr()), dtype, dims, n_cfg, PRECISIONS[precision],
+                                     None if cache_path is None else str(cache_path).encode()))
 
 
 def profile(enable=True):

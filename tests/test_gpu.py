@@ -288,6 +288,40 @@ def test_autotune_cache_and_parity(tmp_path, name, dims, prec):
     check_C(ops.by_name(name), pl, Cb, hu, hd, range(dims[3]), tol=tol)
 
 
+@pytest.mark.parametrize("prec", ["p64", "p32"])
+def test_autotune_batch_cache_and_parity(tmp_path, prec):
+    """The batch tuner times the whole mixed batch, writes one 'batch' line to
+    the cache, leaves the file unchanged when called again for the same
+    batch, and the correlator with the tuned shape matches the oracle."""
+    w = W()
+    plans = [w.plan_std("2H"), w.plan_std("3He")]
+    items = [(0, 0), (1, 1), (1, 2), (0, 2)]
+    dims = (4, 4, 4, 4)
+    hu, hd, du, dd = props(17, 3, dims)
+    path = tmp_path / "tune.txt"
+    w.autotune_batch(plans, items, du, dd, prec, cache_path=path)
+    text = path.read_text()
+    lines = text.splitlines()
+    assert lines[0] == "wick-tune 1"
+    # the file holds every shape tuned in this process; this batch has one line
+    batch = [ln for ln in lines if ln.startswith("batch ") and f":p{w.PRECISIONS[prec]}:" in ln]
+    assert len(batch) == 1 and ":A2K4N6408x2:A3K9N1477440x2 " in batch[0], batch
+    w.autotune_batch(plans, items, du, dd, prec, cache_path=path)
+    assert path.read_text() == text
+    C = w.correlator(plans, items, du, dd, prec, use_graph=True).cpu().numpy()
+    tol = TOL64 if prec == "p64" else SPLIT_TOL[prec]
+    for i, (pi, cfg) in enumerate(items):
+        name = ("2H", "3He")[pi]
+        check_C(ops.by_name(name), plans[pi], _row_as_cfg(C, i, cfg), hu, hd, range(dims[3]), cfg=cfg, tol=tol)
+
+
+def _row_as_cfg(C, i, cfg):
+    """C rows indexed by configuration: item i's row placed at index cfg."""
+    out = np.zeros((cfg + 1,) + C.shape[1:])
+    out[cfg] = C[i]
+    return out
+
+
 # ------------------------------------------------------------- table forms
 @pytest.mark.parametrize("form", ["plain", "packed", "segmented", "segmented-palette"])
 @pytest.mark.parametrize("name,dims", [("2H", (3, 2, 2, 3)), ("3He", (3, 1, 1, 2)), ("3H", (2, 2, 1, 4))])
