@@ -923,7 +923,8 @@ struct BatchEntry {
     BatchContractWork *cwork = nullptr;
     void *partial = nullptr, *B = nullptr, *cpartial = nullptr;
     BatchLaunch L{};
-    hipStream_t cap = nullptr;
+    hipStream_t cap = nullptr, cap1 = nullptr;  // capture streams (phase 0, phase 1)
+    hipEvent_t fork = nullptr, join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t last_use = 0;  // for least-recently-used eviction
@@ -946,6 +947,9 @@ void free_batch(BatchEntry &b)
     if (b.exec) (void)hipGraphExecDestroy(b.exec);
     if (b.graph) (void)hipGraphDestroy(b.graph);
     if (b.cap) (void)hipStreamDestroy(b.cap);
+    if (b.cap1) (void)hipStreamDestroy(b.cap1);
+    if (b.fork) (void)hipEventDestroy(b.fork);
+    if (b.join) (void)hipEventDestroy(b.join);
     for (void *q : {(void *)b.bitems, (void *)b.bwork, (void *)b.bout, (void *)b.citems, (void *)b.cwork, b.partial,
                     b.B, b.cpartial})
         if (q) (void)hipFree(q);
@@ -967,6 +971,18 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
 {
     const int T = dims[3];
     (void)hipGetDevice(&b.device);
+    // two phases of about equal work: the items of each plan dealt alternately
+    // (internal order: phase 0's items, then phase 1's); C keeps the caller's order
+    std::vector<int> order;
+    int n_phase0 = 0;
+    {
+        std::vector<int> byplan(n_items);
+        for (int i = 0; i < n_items; ++i) byplan[i] = i;
+        std::stable_sort(byplan.begin(), byplan.end(), [&](int x, int y) { return items[x].plan < items[y].plan; });
+        for (int pass = 0; pass < 2; ++pass)
+            for (int j = pass; j < n_items; j += 2) order.push_back(byplan[j]);
+        n_phase0 = (n_items + 1) / 2;
+    }
     std::vector<BatchBlockItem> bi(n_items);
     std::vector<BatchBlockWork> bw;
     std::vector<int64_t> bout(n_items + 1, 0);
@@ -975,7 +991,7 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
     int nt_max = 0, passes_max = 1;
     std::vector<DevPlan *> dps(n_items);
     for (int i = 0; i < n_items; ++i) {
-        wick_plan_s *p = plans[items[i].plan];
+        wick_plan_s *p = plans[items[order[i]].plan];
         wick_status st = device_plan(p, nullptr, &dps[i]);
         if (st != WICK_OK) return st;
         DevPlan *dp = dps[i];
@@ -996,7 +1012,7 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
     int64_t total = 0;
     size_t clds = 0;
     for (int i = 0; i < n_items; ++i) {
-        const wick_plan_s *p = plans[items[i].plan];
+        const wick_plan_s *p = plans[items[order[i]].plan];
         const int tg = slices_per_group((int)p->kinds.size(), T);
         if (tg == 0) return fail(WICK_EUNSUPPORTED, "batch: a plan with more than 12 kinds");
         total += p->n_terms * ((T + tg - 1) / tg);
@@ -1007,13 +1023,21 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
     int64_t S = terms_hint > 0 ? terms_hint
                                : std::max<int64_t>(4096, std::min<int64_t>((total + 2047) / 2048, 1 << 20));
     S = (S + kCThreads - 1) / kCThreads * kCThreads;
+    BatchPhase ph[2] = {};
     for (int i = 0; i < n_items; ++i) {
-        wick_plan_s *p = plans[items[i].plan];
+        if (i == 0 || i == n_phase0) {
+            BatchPhase &P = ph[i == 0 ? 0 : 1];
+            P.bw0 = (int)bw.size();
+            P.i0 = i;
+            P.bout0 = bo;
+            P.cw0 = (int)cw.size();
+        }
+        wick_plan_s *p = plans[items[order[i]].plan];
         DevPlan *dp = dps[i];
         const int K = (int)p->kinds.size();
         const int passes = prec == WICK_P64 ? dp->nuc_passes : dp->split_passes;
         bi[i].desc = prec == WICK_P64 ? dp->nuc : dp->nuc_split;
-        bi[i].s_off = (int64_t)items[i].cfg * T * V * 144;
+        bi[i].s_off = (int64_t)items[order[i]].cfg * T * V * 144;
         bi[i].part_off = part;
         bi[i].b_off = bo;
         bi[i].K = K;
@@ -1039,10 +1063,18 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
         c.A = p->A;
         c.K = K;
         c.tg = slices_per_group(K, T);
+        c.out_item = order[i];
         cpart += (int64_t)T * c.n_slices;
         // slice-major (see contract_tg_kernel): one slice's workgroups are adjacent
         for (int sl = 0; sl < c.n_slices; ++sl)
             for (int t0 = 0; t0 < T; t0 += c.tg) cw.push_back({i, t0, sl, std::min(c.tg, T - t0)});
+        if (i + 1 == n_phase0 || i + 1 == n_items) {
+            BatchPhase &P = ph[i + 1 == n_phase0 ? 0 : 1];
+            P.nbw = (int)bw.size() - P.bw0;
+            P.ni = i + 1 - P.i0;
+            P.nbout = bo - P.bout0;
+            P.ncw = (int)cw.size() - P.cw0;
+        }
     }
     bout[n_items] = bo;
     if (bw.size() > 0x7ffffff0ULL || cw.size() > 0x7ffffff0ULL) return fail(WICK_ETOOBIG, "batch too large");
@@ -1057,6 +1089,8 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
         (e = hipMalloc(&b.cpartial, std::max<int64_t>(1, cpart) * 16)) != hipSuccess)
         return fail(WICK_ENOMEM, std::string("batch workspace hipMalloc: ") + hipGetErrorString(e));
     BatchLaunch &L = b.L;
+    L.ph[0] = ph[0];
+    L.ph[1] = ph[1];
     L.Su = S_u;
     L.Sd = S_d;
     L.dtype = dtype;
@@ -1611,13 +1645,18 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
         for (int i = 0; i < n_plans; ++i) b.plans.push_back(plans[i]);
         if (use_graph) {
             hipError_t e;
+            // the two phases as two branches: phase 1's blocks run beside
+            // phase 0's term sum (default-priority streams only)
             if ((e = hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking)) != hipSuccess ||
+                (e = hipStreamCreateWithFlags(&b.cap1, hipStreamNonBlocking)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&b.fork, hipEventDisableTiming)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&b.join, hipEventDisableTiming)) != hipSuccess ||
                 (e = hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
                 free_batch(b);
                 return hip_fail(e, "wick_correlator: graph capture");
             }
             t_capturing = true;
-            hipError_t le = launch_batch(b.L, b.cap);
+            hipError_t le = launch_batch_forked(b.L, b.cap, b.cap1, b.fork, b.join);
             t_capturing = false;
             e = hipStreamEndCapture(b.cap, &b.graph);
             if (le != hipSuccess || e != hipSuccess ||

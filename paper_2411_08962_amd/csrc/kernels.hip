@@ -1161,10 +1161,10 @@ __global__ void contract_finalize_kernel(const double2 *__restrict__ partial, in
 __global__ __launch_bounds__(256) void batch_reduce_kernel(const double2 *__restrict__ partial,
                                                            const BatchBlockItem *__restrict__ items,
                                                            const int64_t *__restrict__ out_off, int n_items,
-                                                           int T, int64_t n_out, double2 *__restrict__ B)
+                                                           int T, int64_t idx0, int64_t n_out, double2 *__restrict__ B)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n_out) return;
+    const int64_t idx = idx0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // outputs [idx0, idx0 + n_out)
+    if (idx >= idx0 + n_out) return;
     int lo = 0, hi = n_items - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -1250,12 +1250,12 @@ __global__ __launch_bounds__(kCThreads) void contract_batch_kernel(const double2
 }
 
 __global__ void batch_finalize_kernel(const double2 *__restrict__ partial,
-                                      const BatchContractItem *__restrict__ items, int n_items, int T,
+                                      const BatchContractItem *__restrict__ items, int i0, int n_items, int T,
                                       double2 *__restrict__ C)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // items [i0, i0 + n_items)
     if (idx >= n_items * T) return;
-    const int i = idx / T, t = idx % T;
+    const int i = i0 + idx / T, t = idx % T;
     const BatchContractItem &it = items[i];
     double sr = 0.0, si = 0.0;
     for (int s = 0; s < it.n_slices; ++s) {
@@ -1263,7 +1263,7 @@ __global__ void batch_finalize_kernel(const double2 *__restrict__ partial,
         sr += v.x;
         si += v.y;
     }
-    C[idx] = double2{sr, si};
+    C[(int64_t)it.out_item * T + t] = double2{sr, si};
 }
 
 int round8(int64_t n) { return (int)((n + 7) / 8 * 8); }
@@ -1441,22 +1441,25 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t s)
 }
 
 
-hipError_t launch_batch(const BatchLaunch &L, hipStream_t s)
+namespace {
+// The four launches of a batch phase, one kernel at a time; kernel k in
+// {0: blocks, 1: block reduction, 2: term sum, 3: finalize}.
+hipError_t batch_kernel(const BatchLaunch &L, const BatchPhase &P, int k, hipStream_t s)
 {
-    {
-        Probe pr("blocks", s);
-        const unsigned blocks = (unsigned)round8((int64_t)L.n_bwork * kNucColGroups);
+    if (k == 0 && P.nbw > 0) {
+        const unsigned blocks = (unsigned)round8((int64_t)P.nbw * kNucColGroups);
+        const BatchBlockWork *bw = L.bwork + P.bw0;
         bool done = false;
 #define WICK_BNUC(NTV, MODE)                                                                                      \
     if (L.nt_max == NTV && L.prec == MODE) {                                                                      \
         if (L.dtype == 0)                                                                                         \
             hipLaunchKernelGGL((blocks_nucleon_kernel<double2, NTV, MODE>), dim3(blocks), dim3(kNucThreads), 0,    \
                                s, (const double2 *)L.Su, (const double2 *)L.Sd, nullptr, L.V, L.chunk_sites, 0, 0, \
-                               L.n_bwork, (double2 *)L.partial, L.bitems, L.bwork, L.T);                         \
+                               P.nbw, (double2 *)L.partial, L.bitems, bw, L.T);                                   \
         else                                                                                                      \
             hipLaunchKernelGGL((blocks_nucleon_kernel<float2, NTV, MODE>), dim3(blocks), dim3(kNucThreads), 0,     \
                                s, (const float2 *)L.Su, (const float2 *)L.Sd, nullptr, L.V, L.chunk_sites, 0, 0,   \
-                               L.n_bwork, (double2 *)L.partial, L.bitems, L.bwork, L.T);                         \
+                               P.nbw, (double2 *)L.partial, L.bitems, bw, L.T);                                   \
         done = true;                                                                                              \
     }
         WICK_BNUC(1, WICK_P64) WICK_BNUC(2, WICK_P64) WICK_BNUC(3, WICK_P64) WICK_BNUC(4, WICK_P64)
@@ -1465,34 +1468,52 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t s)
         WICK_BNUC(1, WICK_PB6) WICK_BNUC(2, WICK_PB6) WICK_BNUC(3, WICK_PB6)
 #undef WICK_BNUC
         if (!done) return hipErrorInvalidValue;
-        pr.stop();
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    {
-        Probe pr("blocks_reduce", s);
-        hipLaunchKernelGGL(batch_reduce_kernel, dim3((unsigned)((L.n_bout + 255) / 256)), dim3(256), 0, s,
-                           (const double2 *)L.partial, L.bitems, L.bout_off, L.n_items, L.T, L.n_bout, (double2 *)L.B);
-        pr.stop();
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    {
-        Probe pr("contract", s);
+    } else if (k == 1 && P.nbout > 0) {
+        hipLaunchKernelGGL(batch_reduce_kernel, dim3((unsigned)((P.nbout + 255) / 256)), dim3(256), 0, s,
+                           (const double2 *)L.partial, L.bitems, L.bout_off, L.n_items, L.T, P.bout0, P.nbout,
+                           (double2 *)L.B);
+    } else if (k == 2 && P.ncw > 0) {
         if (L.contract_lds > kMaxContractLds) return hipErrorInvalidValue;
         static const hipError_t attr = allow_lds(contract_batch_kernel);
         if (attr != hipSuccess) return attr;
-        hipLaunchKernelGGL(contract_batch_kernel, dim3((unsigned)round8(L.n_cwork)), dim3(kCThreads), L.contract_lds,
-                           s, (const double2 *)L.B, L.citems, L.cwork, L.n_cwork, (double2 *)L.cpartial);
-        pr.stop();
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(contract_batch_kernel, dim3((unsigned)round8(P.ncw)), dim3(kCThreads), L.contract_lds, s,
+                           (const double2 *)L.B, L.citems, L.cwork + P.cw0, P.ncw, (double2 *)L.cpartial);
+    } else if (k == 3 && P.ni > 0) {
+        hipLaunchKernelGGL(batch_finalize_kernel, dim3((P.ni * L.T + 255) / 256), dim3(256), 0, s,
+                           (const double2 *)L.cpartial, L.citems, P.i0, P.ni, L.T, (double2 *)L.C);
     }
-    Probe pr("contract_finalize", s);
-    hipLaunchKernelGGL(batch_finalize_kernel, dim3((L.n_items * L.T + 255) / 256), dim3(256), 0, s,
-                       (const double2 *)L.cpartial, L.citems, L.n_items, L.T, (double2 *)L.C);
-    pr.stop();
     return hipGetLastError();
+}
+const char *const kBatchKernelName[4] = {"blocks", "blocks_reduce", "contract", "contract_finalize"};
+}  // namespace
+
+hipError_t launch_batch(const BatchLaunch &L, hipStream_t s)
+{
+    // kernel by kernel over both phases (the per-kernel timings then cover the whole batch)
+    for (int k = 0; k < 4; ++k) {
+        Probe pr(kBatchKernelName[k], s);
+        for (int ph = 0; ph < 2; ++ph) {
+            const hipError_t e = batch_kernel(L, L.ph[ph], k, s);
+            if (e != hipSuccess) return e;
+        }
+        pr.stop();
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_batch_forked(const BatchLaunch &L, hipStream_t s0, hipStream_t s1, hipEvent_t fork,
+                               hipEvent_t join)
+{
+    hipError_t e;
+    for (int k = 0; k < 2; ++k)
+        if ((e = batch_kernel(L, L.ph[0], k, s0)) != hipSuccess) return e;
+    if ((e = hipEventRecord(fork, s0)) != hipSuccess || (e = hipStreamWaitEvent(s1, fork, 0)) != hipSuccess) return e;
+    for (int k = 2; k < 4; ++k)
+        if ((e = batch_kernel(L, L.ph[0], k, s0)) != hipSuccess) return e;
+    for (int k = 0; k < 4; ++k)
+        if ((e = batch_kernel(L, L.ph[1], k, s1)) != hipSuccess) return e;
+    if ((e = hipEventRecord(join, s1)) != hipSuccess || (e = hipStreamWaitEvent(s0, join, 0)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 }  // namespace wick

@@ -135,6 +135,7 @@ struct BatchContractItem {
     TermTable tab;
     int64_t N, slice_len, b_off, part_off;  // part_off: first partial of (item, t = 0); slice_len in chunks when segmented
     int32_t A, K, n_slices, tg;
+    int32_t out_item;                       // the item's row of C (the caller's item index)
 };
 struct BatchContractWork {
     int32_t item, t0, slice, ntg;
@@ -160,7 +161,17 @@ struct BlockLaunch {
 
 hipError_t launch_blocks(const BlockLaunch &L, hipStream_t s);
 
+// A batch runs in two phases of about equal work (items dealt alternately);
+// each phase's work is a contiguous range of every work list, so phase 1's
+// blocks can run while phase 0's term sum does (launch_batch_forked).
+struct BatchPhase {
+    int bw0, nbw;          // block work entries
+    int i0, ni;            // items (internal order)
+    int64_t bout0, nbout;  // block outputs
+    int cw0, ncw;          // term-sum work entries
+};
 struct BatchLaunch {
+    BatchPhase ph[2];
     const void *Su, *Sd;
     int dtype, prec, nt_max;
     int64_t V;
@@ -180,7 +191,12 @@ struct BatchLaunch {
     double *cpartial;                 // contraction partials
     double *C;                        // [n_items][T][2]
 };
-hipError_t launch_batch(const BatchLaunch &L, hipStream_t s);
+hipError_t launch_batch(const BatchLaunch &L, hipStream_t s);  // both phases in order on one stream
+// Phase 0 on s0; phase 1 forked onto s1 after phase 0's blocks, so its blocks
+// overlap phase 0's term sum; s0 then waits for s1 (graph capture makes the
+// fork and join graph edges). fork/join: events owned by the caller.
+hipError_t launch_batch_forked(const BatchLaunch &L, hipStream_t s0, hipStream_t s1, hipEvent_t fork,
+                               hipEvent_t join);
 
 struct ContractLaunch {
     const double *B;         // [n_ct][K][792][2]
