@@ -690,6 +690,17 @@ int64_t tuned_slice(const wick_plan_s *p, int64_t n_ct)
     return it == g_slice.end() ? 0 : it->second;
 }
 
+// workgroups sharing one table slice in the term sum (ContractLaunch::share),
+// under the same key; 1 (group-major order) unless tuned
+std::map<std::string, int> g_share;
+
+int tuned_share(const wick_plan_s *p, int64_t n_ct)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_share.find(slice_key(p, n_ct));
+    return it == g_share.end() ? 1 : it->second;
+}
+
 // batched launches tuned as a whole: (block sites per workgroup, terms per
 // term-sum workgroup), keyed by the lattice, storage, precision and the
 // multiset of the items' tables (which configuration an item reads does not
@@ -834,7 +845,7 @@ wick_status resident_plan(wick_plan_s *p, DevPlan **out)
 // device, and nothing is allocated; a launch needing more than cap bytes of
 // partial sums is WICK_ETOOBIG.
 wick_status do_contract(wick_plan_s *p, const double *B, int n_cfg, int T, hipStream_t s, double *C,
-                        int64_t slice_override = 0, void *fixed = nullptr, size_t cap = 0)
+                        int64_t slice_override = 0, void *fixed = nullptr, size_t cap = 0, int share_override = 0)
 {
     if (!B || !C) return fail(WICK_EINVAL, "wick_contract: null pointer");
     if (n_cfg < 1 || T < 1) return fail(WICK_EINVAL, "wick_contract: n_cfg and T must be >= 1");
@@ -854,6 +865,7 @@ wick_status do_contract(wick_plan_s *p, const double *B, int n_cfg, int T, hipSt
     L.N = p->n_terms;
     L.n_ct = (int)n_ct;
     L.tg = slices_per_group(L.K, n_ct);
+    L.share = share_override > 0 ? share_override : tuned_share(p, n_ct);
     const int64_t n_groups = L.tg ? (n_ct + L.tg - 1) / L.tg : n_ct;
     const int64_t sl = slice_override > 0 ? slice_override : tuned_slice(p, n_ct);
     L.slice_len = sl > 0 ? sl : default_slice_len(L.N, n_groups);
@@ -1130,6 +1142,7 @@ wick_status load_tune_file(const char *path)
     std::map<std::string, Tune> tb;
     std::map<std::string, int64_t> ts;
     std::map<std::string, std::pair<int, int64_t>> tbt;
+    std::map<std::string, int> tsh;
     int ln = 1;
     while (std::getline(f, line)) {
         ++ln;
@@ -1147,6 +1160,10 @@ wick_status load_tune_file(const char *path)
             int64_t v = 0;
             ok = static_cast<bool>(is >> c >> v) && c >= 4 && c <= (1 << 24) && v >= 1024 && v <= (1LL << 30);
             if (ok) tbt[key] = {c, v};
+        } else if (ok && what == "share") {
+            int v = 0;
+            ok = static_cast<bool>(is >> v) && v >= 1 && v <= 64;
+            if (ok) tsh[key] = v;
         } else if (ok && what == "contract") {
             int64_t v = 0;
             ok = static_cast<bool>(is >> v) && v >= 1 && v <= (1LL << 30);  // terms or chunks per workgroup
@@ -1161,6 +1178,7 @@ wick_status load_tune_file(const char *path)
     for (auto &kv : tb) g_tune[kv.first] = kv.second;
     for (auto &kv : ts) g_slice[kv.first] = kv.second;
     for (auto &kv : tbt) g_batch_tune[kv.first] = kv.second;
+    for (auto &kv : tsh) g_share[kv.first] = kv.second;
     return WICK_OK;
 }
 
@@ -1175,6 +1193,7 @@ wick_status save_tune_file(const char *path)
         for (auto &kv : g_tune) f << "blocks " << kv.first << ' ' << kv.second.chunk_sites << ' '
                                   << kv.second.batch_chunk_sites << "\n";
         for (auto &kv : g_slice) f << "contract " << kv.first << ' ' << kv.second << "\n";
+        for (auto &kv : g_share) f << "share " << kv.first << ' ' << kv.second << "\n";
         for (auto &kv : g_batch_tune)
             f << "batch " << kv.first << ' ' << kv.second.first << ' ' << kv.second.second << "\n";
         if (!f) return fail(WICK_EINVAL, std::string("cannot write tune cache ") + tmp);
@@ -1273,6 +1292,7 @@ wick_status autotune(wick_plan_s *p, const int32_t dims[4], int dtype, int prec,
 
     // term sum: terms per workgroup
     int64_t best_slice = 0;
+    int best_share = 1;
     if (p->n_terms > 0) {
         if ((st = do_blocks(p, sc.Su, sc.Sd, dtype, dims, 1, prec, sc.s, (double *)sc.B, best_chunk)) != WICK_OK)
             return st;
@@ -1285,6 +1305,16 @@ wick_status autotune(wick_plan_s *p, const int32_t dims[4], int dtype, int prec,
                            &ms);
             if (st != WICK_OK) return st;
             if (!best_slice || ms < best) { best = ms; best_slice = sl; }
+        }
+        // then how many groups of slices read one table slice together
+        for (int h : {2, 4}) {
+            if (h > (T + 2) / 3) break;  // fewer groups of slices than h
+            float ms = 0.f;
+            st = time_runs(sc.s, 3, [&] {
+                return do_contract(p, (const double *)sc.B, 1, T, sc.s, (double *)sc.C, best_slice, nullptr, 0, h);
+            }, &ms);
+            if (st != WICK_OK) return st;
+            if (ms < best) { best = ms; best_share = h; }
         }
     }
 
@@ -1313,6 +1343,7 @@ wick_status autotune(wick_plan_s *p, const int32_t dims[4], int dtype, int prec,
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[key] = Tune{best_chunk, best_batch};
         if (best_slice > 0) g_slice[skey] = best_slice;
+        if (best_slice > 0) g_share[skey] = best_share;
     }
     return cache_path ? save_tune_file(cache_path) : WICK_OK;
 }

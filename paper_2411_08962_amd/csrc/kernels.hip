@@ -1105,17 +1105,32 @@ __device__ __forceinline__ void reduce_tg(double (&ar)[kMaxTG], double (&ai)[kMa
 template <int A, int FORM>
 __global__ __launch_bounds__(kCThreads) void contract_tg_kernel(const double2 *__restrict__ B, TermTable tab,
                                                                 int64_t N, int K, int n_ct, int tg, int n_slices,
-                                                                int64_t slice_len, double2 *__restrict__ partial)
+                                                                int64_t slice_len, double2 *__restrict__ partial,
+                                                                int share)
 {
     extern __shared__ double2 lds[];
     __shared__ double red[kMaxTG][2][kCThreads / 64];
     const int n_groups = (n_ct + tg - 1) / tg;
     const int lb = xcd_block();
     if (lb >= n_groups * n_slices) return;
-    // group-major: adjacent workgroups share their staged blocks (measured
-    // faster than slice-major for one plan; the batched path orders its work
-    // list slice-major, measured faster there)
-    const int g = lb / n_slices, slice = lb % n_slices;
+    // share = 1: group-major (adjacent workgroups share their staged blocks);
+    // share = h > 1: h adjacent workgroups (one XCD) take h groups of slices
+    // at one table slice, so the slice is read from HBM about once per h
+    // groups and shared through that XCD's L2
+    int g, slice;
+    {
+        const int h = share < 1 ? 1 : (share > n_groups ? n_groups : share);
+        const int full = n_groups / h, rem = n_groups % h;
+        if (lb < full * h * n_slices) {
+            const int rest = lb / h;
+            slice = rest % n_slices;
+            g = (rest / n_slices) * h + lb % h;
+        } else {
+            const int l2 = lb - full * h * n_slices;
+            slice = l2 / rem;
+            g = full * h + l2 % rem;
+        }
+    }
     const int ct0 = g * tg, ntg = n_ct - ct0 < tg ? n_ct - ct0 : tg;
     const int KB = K * 792;
     double2 *spal = lds, *sB = lds + kMaxPalette;
@@ -1361,7 +1376,7 @@ template <int A, int FORM> hipError_t launch_tg(const ContractLaunch &L, hipStre
     if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((contract_tg_kernel<A, FORM>), dim3(blocks), dim3(kCThreads),
                        contract_tg_lds_bytes(L.K, L.tg), s, (const double2 *)L.B, L.tab, L.N, L.K, L.n_ct, L.tg,
-                       L.n_slices, L.slice_len, (double2 *)L.partial);
+                       L.n_slices, L.slice_len, (double2 *)L.partial, L.share);
     return hipSuccess;
 }
 

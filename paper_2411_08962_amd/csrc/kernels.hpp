@@ -207,6 +207,7 @@ struct ContractLaunch {
     int tg;                  // time slices per workgroup (LDS kernel); 0: blocks read from global memory
     int n_slices;
     int64_t slice_len;       // terms per workgroup (chunks per workgroup for a segmented table)
+    int share;               // groups of slices taking one table slice together (1: group-major)
     double *partial;         // [n_ct][n_slices][2]
     double *C;               // [n_ct][2]
 };
