@@ -204,17 +204,25 @@ int32_t integer_unit(const wick_plan_s *p)
 
 // LDS bank balance of the gathers of integer-coefficient words. Step j of a
 // chunk gathers, for each lane, the node entry, leaf 0 and leaf 1 of the
-// lane's j-th word, as three wave-wide 16-byte LDS reads. A 16-byte entry e
-// lies in bank group e mod 16, and such a read takes longer the more lanes
-// of one half-wave hit the same group (measured on MI355X: about 1.45x from
-// random entries to at most two lanes per group). The sum of a segment does
-// not depend on the order of its words, so each lane's words are reordered
-// greedily: at each step the lanes of a half-wave in turn take, among their
-// next kBalanceWindow words, the one whose three groups are least used so
-// far at that step. Chunks are independent (host threads).
+// lane's j-th word, as three wave-wide 16-byte LDS reads. A 16-byte slot s
+// lies in bank group s mod 16, and such a read takes longer the more lanes
+// hit the same group (measured on MI355X: 13.5 cycles per wave-wide read for
+// random slots; 9.3 when each group is hit at most twice per half-wave or per
+// quarter-wave; 6.3 when in addition every quarter-wave uses the same
+// lane-to-group pattern). The sum of a segment does not depend on the order
+// of its words, so each lane's words are reordered greedily: at each step the
+// lanes of a half-wave in turn take, among their next kBalanceWindow words,
+// the one whose three groups are least used so far in that half-wave at that
+// step (balancing per quarter-wave instead measured 2 % slower on the
+// 64-configuration batch). Chunks are independent (host threads).
+int slices_per_group(int K, int64_t n_sets);
 constexpr int kBalanceWindow = 16;
-void balance_banks(SegTable &out, const std::vector<int32_t> &lane_len)
+constexpr uint64_t kIdxMask = (1u << kPackBits) - 1;
+void balance_banks(SegTable &out, const std::vector<int32_t> &lane_len, int ntg)
 {
+    // LDS bank group of entry e: the term sum interleaves ntg slices, entry e of
+    // slice 0 at 16-byte slot e * ntg (slice t adds t to every lane alike)
+    auto grp = [ntg](uint64_t e) { return (int)((e * (uint64_t)ntg) & 15); };
     const size_t n_chunks = out.base.size();
     auto work = [&](size_t c_lo, size_t c_hi) {
         for (size_t c = c_lo; c < c_hi; ++c) {
@@ -230,15 +238,15 @@ void balance_banks(SegTable &out, const std::vector<int32_t> &lane_len)
                         int best = j, best_cost = 1 << 30;
                         for (int k = j; k < end; ++k) {
                             const uint64_t v = w[(size_t)k * 64 + l];
-                            int cost = cnt[0][(v >> kPackBits) & 15] + cnt[1][v & 15];
-                            if (v >> 53) cost += cnt[2][(v >> (2 * kPackBits)) & 15];
+                            int cost = cnt[0][grp((v >> kPackBits) & kIdxMask)] + cnt[1][grp(v & kIdxMask)];
+                            if (v >> 53) cost += cnt[2][grp((v >> (2 * kPackBits)) & kIdxMask)];
                             if (cost < best_cost) { best_cost = cost; best = k; }
                         }
                         std::swap(w[(size_t)j * 64 + l], w[(size_t)best * 64 + l]);
                         const uint64_t v = w[(size_t)j * 64 + l];
-                        ++cnt[0][(v >> kPackBits) & 15];
-                        ++cnt[1][v & 15];
-                        if (v >> 53) ++cnt[2][(v >> (2 * kPackBits)) & 15];
+                        ++cnt[0][grp((v >> kPackBits) & kIdxMask)];
+                        ++cnt[1][grp(v & kIdxMask)];
+                        if (v >> 53) ++cnt[2][grp((v >> (2 * kPackBits)) & kIdxMask)];
                     }
                 }
         }
@@ -350,7 +358,7 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
         // variable turns it off, for measurement)
         std::vector<int32_t> lane_len(n_chunks * 64, 0);
         for (size_t si = 0; si < segs.size(); ++si) lane_len[si] = (int32_t)segs[si].second;
-        balance_banks(out, lane_len);
+        balance_banks(out, lane_len, slices_per_group((int)p->kinds.size(), kMaxTG));
     }
     return true;
 }
@@ -705,7 +713,12 @@ int tuned_share(const wick_plan_s *p, int64_t n_ct)
 // term-sum workgroup), keyed by the lattice, storage, precision and the
 // multiset of the items' tables (which configuration an item reads does not
 // change the launch)
-std::map<std::string, std::pair<int, int64_t>> g_batch_tune;
+struct BatchTune {
+    int chunk = 0;
+    int64_t terms = 0;
+    int share = 2;
+};
+std::map<std::string, BatchTune> g_batch_tune;
 
 std::string batch_key(const wick_plan_t *plans, const wick_item *items, int n_items, const int32_t dims[4], int dtype,
                       int prec)
@@ -723,13 +736,12 @@ std::string batch_key(const wick_plan_t *plans, const wick_item *items, int n_it
     return o.str();
 }
 
-bool tuned_batch(const std::string &key, int *chunk, int64_t *terms)
+bool tuned_batch(const std::string &key, BatchTune *out)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_batch_tune.find(key);
     if (it == g_batch_tune.end()) return false;
-    *chunk = it->second.first;
-    *terms = it->second.second;
+    *out = it->second;
     return true;
 }
 
@@ -979,8 +991,9 @@ template <class T> wick_status upload(const std::vector<T> &h, T **d)
 
 wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_items, const void *S_u,
                         const void *S_d, int dtype, const int32_t dims[4], int64_t V, int prec, int chunk_hint,
-                        double *C, BatchEntry &b, int64_t terms_hint = 0)
+                        double *C, BatchEntry &b, int64_t terms_hint = 0, int share = 2)
 {
+    share = std::max(1, share);
     const int T = dims[3];
     (void)hipGetDevice(&b.device);
     // two phases of about equal work: the items of each plan dealt alternately
@@ -1077,9 +1090,16 @@ wick_status build_batch(const wick_plan_t *plans, const wick_item *items, int n_
         c.tg = slices_per_group(K, T);
         c.out_item = order[i];
         cpart += (int64_t)T * c.n_slices;
-        // slice-major (see contract_tg_kernel): one slice's workgroups are adjacent
-        for (int sl = 0; sl < c.n_slices; ++sl)
-            for (int t0 = 0; t0 < T; t0 += c.tg) cw.push_back({i, t0, sl, std::min(c.tg, T - t0)});
+        // `share` groups of time slices take each table slice together (adjacent
+        // workgroups, one XCD: the slice is shared through its L2), then the
+        // next `share` groups (see contract_tg_kernel)
+        const int n_tgroups = (T + c.tg - 1) / c.tg;
+        for (int g0 = 0; g0 < n_tgroups; g0 += share)
+            for (int sl = 0; sl < c.n_slices; ++sl)
+                for (int gg = g0; gg < std::min(n_tgroups, g0 + share); ++gg) {
+                    const int t0 = gg * c.tg;
+                    cw.push_back({i, t0, sl, std::min(c.tg, T - t0)});
+                }
         if (i + 1 == n_phase0 || i + 1 == n_items) {
             BatchPhase &P = ph[i + 1 == n_phase0 ? 0 : 1];
             P.nbw = (int)bw.size() - P.bw0;
@@ -1141,7 +1161,7 @@ wick_status load_tune_file(const char *path)
         return fail(WICK_ECORRUPT, std::string("tune cache ") + path + ": bad header");
     std::map<std::string, Tune> tb;
     std::map<std::string, int64_t> ts;
-    std::map<std::string, std::pair<int, int64_t>> tbt;
+    std::map<std::string, BatchTune> tbt;
     std::map<std::string, int> tsh;
     int ln = 1;
     while (std::getline(f, line)) {
@@ -1156,10 +1176,10 @@ wick_status load_tune_file(const char *path)
                  t.chunk_sites <= (1 << 24) && t.batch_chunk_sites >= 0 && t.batch_chunk_sites <= (1 << 24);
             if (ok) tb[key] = t;
         } else if (ok && what == "batch") {
-            int c = 0;
-            int64_t v = 0;
-            ok = static_cast<bool>(is >> c >> v) && c >= 4 && c <= (1 << 24) && v >= 1024 && v <= (1LL << 30);
-            if (ok) tbt[key] = {c, v};
+            BatchTune bt;
+            ok = static_cast<bool>(is >> bt.chunk >> bt.terms >> bt.share) && bt.chunk >= 4 && bt.chunk <= (1 << 24) &&
+                 bt.terms >= 1024 && bt.terms <= (1LL << 30) && bt.share >= 1 && bt.share <= 64;
+            if (ok) tbt[key] = bt;
         } else if (ok && what == "share") {
             int v = 0;
             ok = static_cast<bool>(is >> v) && v >= 1 && v <= 64;
@@ -1195,7 +1215,8 @@ wick_status save_tune_file(const char *path)
         for (auto &kv : g_slice) f << "contract " << kv.first << ' ' << kv.second << "\n";
         for (auto &kv : g_share) f << "share " << kv.first << ' ' << kv.second << "\n";
         for (auto &kv : g_batch_tune)
-            f << "batch " << kv.first << ' ' << kv.second.first << ' ' << kv.second.second << "\n";
+            f << "batch " << kv.first << ' ' << kv.second.chunk << ' ' << kv.second.terms << ' ' << kv.second.share
+              << "\n";
         if (!f) return fail(WICK_EINVAL, std::string("cannot write tune cache ") + tmp);
     }
     if (std::rename(tmp.c_str(), path) != 0) return fail(WICK_EINVAL, std::string("cannot replace ") + path);
@@ -1390,10 +1411,10 @@ wick_status autotune_batch(const wick_plan_t *plans, int n_plans, const wick_ite
         return fail(WICK_ENOMEM, std::string("wick_autotune_batch hipMalloc: ") + hipGetErrorString(e));
     if ((e = hipStreamCreateWithFlags(&sc.s, hipStreamNonBlocking)) != hipSuccess)
         return hip_fail(e, "wick_autotune_batch stream");
-    auto run = [&](int chunk, int64_t terms, float *ms) {
+    auto run = [&](int chunk, int64_t terms, int share, float *ms) {
         BatchEntry b;
         wick_status r = build_batch(plans, items, n_items, S_u, S_d, dtype, dims, V, prec, chunk, (double *)sc.C, b,
-                                    terms);
+                                    terms, share);
         if (r == WICK_OK)
             r = time_runs(sc.s, 2, [&] {
                 hipError_t le = launch_batch(b.L, sc.s);
@@ -1408,19 +1429,26 @@ wick_status autotune_batch(const wick_plan_t *plans, int n_plans, const wick_ite
         const int c = (int)((V + div - 1) / div + 7) / 8 * 8;
         if (div > 1 && c < 256) break;
         float ms = 0.f;
-        if ((st = run(c, 0, &ms)) != WICK_OK) return st;
+        if ((st = run(c, 0, 2, &ms)) != WICK_OK) return st;
         if (!best_chunk || ms < best) { best = ms; best_chunk = c; }
     }
     int64_t best_terms = 0;
     best = 0.f;
     for (int64_t S = 1 << 16; S <= (1 << 22); S *= 2) {
         float ms = 0.f;
-        if ((st = run(best_chunk, S, &ms)) != WICK_OK) return st;
+        if ((st = run(best_chunk, S, 2, &ms)) != WICK_OK) return st;
         if (!best_terms || ms < best) { best = ms; best_terms = S; }
+    }
+    // groups of time slices that take a table slice together
+    int best_share = 2;
+    for (int h : {1, 4, 16}) {
+        float ms = 0.f;
+        if ((st = run(best_chunk, best_terms, h, &ms)) != WICK_OK) return st;
+        if (ms < best) { best = ms; best_share = h; }
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_batch_tune[key] = {best_chunk, best_terms};
+        g_batch_tune[key] = BatchTune{best_chunk, best_terms, best_share};
     }
     return cache_path ? save_tune_file(cache_path) : WICK_OK;
 }
@@ -1664,11 +1692,11 @@ wick_status wick_correlator(const wick_plan_t *plans, int32_t n_plans, const wic
         BatchEntry b;
         // launch shape: tuned for this batch (wick_autotune_batch), else the
         // first plan's batched block shape and the default term split
-        int chunk = tune_for(plans[0], dims, (int)dtype, (int)prec).batch_chunk_sites;
-        int64_t terms = 0;
-        (void)tuned_batch(batch_key(plans, items, n_items, dims, (int)dtype, (int)prec), &chunk, &terms);
-        WICK_TRY(st = build_batch(plans, items, n_items, S_u, S_d, (int)dtype, dims, V, (int)prec, chunk, C, b,
-                                  terms));
+        BatchTune bt;
+        bt.chunk = tune_for(plans[0], dims, (int)dtype, (int)prec).batch_chunk_sites;
+        (void)tuned_batch(batch_key(plans, items, n_items, dims, (int)dtype, (int)prec), &bt);
+        WICK_TRY(st = build_batch(plans, items, n_items, S_u, S_d, (int)dtype, dims, V, (int)prec, bt.chunk, C, b,
+                                  bt.terms, bt.share));
         if (st != WICK_OK) {
             free_batch(b);
             return st;

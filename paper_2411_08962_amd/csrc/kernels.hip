@@ -973,15 +973,19 @@ __device__ __forceinline__ void term_sum_seg(const double2 *__restrict__ sB, int
 // Term sum over the chunks [c0, c1) of a segmented table with
 // integer-coefficient words, for NTG staged slices (a compile-time count, so
 // that the gathers of every slice are issued together and one wait covers
-// them). A missing leaf (q = 0) and a padding word read entry 0 and weigh it
-// by zero; lanes reading one address share the read.
+// them). The slices' blocks are interleaved in LDS, entry e of slice s at
+// sB[e * NTG + s] (stage_blocks_interleaved), so the NTG gathers of one entry
+// share one address and differ by an immediate offset. A missing leaf (q = 0)
+// and a padding word read entry 0 and weigh it by zero; lanes reading one
+// address share the read. The coefficients are the integers q; the table's
+// unit multiplies each segment's sum once.
 template <int A, int NTG>
-__device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, int KB, const TermTable &tab, int c0,
-                                              int c1, double (&ar)[kMaxTG], double (&ai)[kMaxTG])
+__device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, const TermTable &tab, int c0, int c1,
+                                              double (&ar)[kMaxTG], double (&ai)[kMaxTG])
 {
     constexpr uint32_t kMask = (1u << kPackBits) - 1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int unit = tab.coef_unit;
+    const double unit = (double)tab.coef_unit;
     for (int c = c0 + wave; c < c1; c += kCThreads / 64) {
         const uint32_t pre = tab.seg_prefix[(int64_t)c * 64 + lane];
         double sx[NTG], sy[NTG];
@@ -990,24 +994,30 @@ __device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, in
         const uint64_t *wp = tab.words + tab.chunk_base[c] + lane;
         const int nodes = tab.chunk_len[c];  // uniform over the wave
         auto eval = [&](uint64_t w) {
-            const int l0 = (int)(w & kMask), in = (int)((w >> kPackBits) & kMask);
-            const int l1 = (int)((w >> (2 * kPackBits)) & kMask);
-            const double cf0 = (double)((int)((int64_t)(w << 11) >> 53) * unit);
-            const double cf1 = (double)((int)((int64_t)w >> 53) * unit);
+            const double2 *pn = sB + (int)((w >> kPackBits) & kMask) * NTG;
+            const double2 *p0 = sB + (int)(w & kMask) * NTG;
+            const double2 *p1 = sB + (int)((w >> (2 * kPackBits)) & kMask) * NTG;
+            // q of leaf 0 is bits [42, 53) and q of leaf 1 bits [53, 64) of the
+            // word: bits [10, 21) and [21, 32) of its high half (32-bit
+            // arithmetic shifts sign-extend them)
+            const uint32_t hi = (uint32_t)(w >> 32);
+            const double cf0 = (double)((int)(hi << 11) >> 21);
+            const double cf1 = (double)((int)hi >> 21);
             double2 b0[NTG], b1[NTG], bn[NTG];
 #pragma unroll
             for (int tg = 0; tg < NTG; ++tg) {
-                const double2 *Bt = sB + tg * KB;
-                bn[tg] = Bt[in];
-                b0[tg] = Bt[l0];
-                b1[tg] = Bt[l1];
+                bn[tg] = pn[tg];
+                b0[tg] = p0[tg];
+                b1[tg] = p1[tg];
             }
 #pragma unroll
             for (int tg = 0; tg < NTG; ++tg) {
                 const double s3x = fma(cf1, b1[tg].x, cf0 * b0[tg].x);
                 const double s3y = fma(cf1, b1[tg].y, cf0 * b0[tg].y);
-                sx[tg] += bn[tg].x * s3x - bn[tg].y * s3y;
-                sy[tg] += bn[tg].x * s3y + bn[tg].y * s3x;
+                sx[tg] = fma(bn[tg].x, s3x, sx[tg]);
+                sx[tg] = fma(-bn[tg].y, s3y, sx[tg]);
+                sy[tg] = fma(bn[tg].x, s3y, sy[tg]);
+                sy[tg] = fma(bn[tg].y, s3x, sy[tg]);
             }
         };
         // the words of the next kPrefetch nodes are loaded while the current
@@ -1031,10 +1041,10 @@ __device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, in
         }
 #pragma unroll
         for (int tg = 0; tg < NTG; ++tg) {
-            double px = 1.0, py = 0.0;
+            double px = unit, py = 0.0;
 #pragma unroll
             for (int a = 0; a < A - 2; ++a) {
-                const double2 b = sB[tg * KB + ((pre >> (kPackBits * a)) & kMask)];
+                const double2 b = sB[(int)((pre >> (kPackBits * a)) & kMask) * NTG + tg];
                 const double x = px * b.x - py * b.y;
                 py = px * b.y + py * b.x;
                 px = x;
@@ -1046,13 +1056,25 @@ __device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, in
 }
 
 template <int A>
-__device__ __forceinline__ void term_sum_segi_n(const double2 *__restrict__ sB, int KB, int ntg, const TermTable &tab,
-                                                int c0, int c1, double (&ar)[kMaxTG], double (&ai)[kMaxTG])
+__device__ __forceinline__ void term_sum_segi_n(const double2 *__restrict__ sB, int ntg, const TermTable &tab, int c0,
+                                                int c1, double (&ar)[kMaxTG], double (&ai)[kMaxTG])
 {
     static_assert(kMaxTG == 3, "one instance per slice count");
-    if (ntg == 3) term_sum_segi<A, 3>(sB, KB, tab, c0, c1, ar, ai);
-    else if (ntg == 2) term_sum_segi<A, 2>(sB, KB, tab, c0, c1, ar, ai);
-    else term_sum_segi<A, 1>(sB, KB, tab, c0, c1, ar, ai);
+    if (ntg == 3) term_sum_segi<A, 3>(sB, tab, c0, c1, ar, ai);
+    else if (ntg == 2) term_sum_segi<A, 2>(sB, tab, c0, c1, ar, ai);
+    else term_sum_segi<A, 1>(sB, tab, c0, c1, ar, ai);
+}
+
+// Stage ntg slices of KB block entries each (contiguous in B), interleaved:
+// entry e of slice t at sB[e * ntg + t] (integer-coefficient segmented tables).
+__device__ __forceinline__ void stage_blocks_interleaved(const double2 *__restrict__ Bsrc, int KB, int ntg,
+                                                         double2 *__restrict__ sB)
+{
+    for (int i = threadIdx.x; i < ntg * KB; i += kCThreads) {
+        const int t = i / KB, e = i - t * KB;
+        sB[e * ntg + t] = Bsrc[i];
+    }
+    __syncthreads();
 }
 
 // Stage ntg slices of K blocks (contiguous in B) and the palette.
@@ -1134,12 +1156,13 @@ __global__ __launch_bounds__(kCThreads) void contract_tg_kernel(const double2 *_
     const int ct0 = g * tg, ntg = n_ct - ct0 < tg ? n_ct - ct0 : tg;
     const int KB = K * 792;
     double2 *spal = lds, *sB = lds + kMaxPalette;
-    stage_blocks(B + (int64_t)ct0 * KB, ntg * KB, tab, sB, spal);
+    if constexpr (FORM == 5) stage_blocks_interleaved(B + (int64_t)ct0 * KB, KB, ntg, sB);
+    else stage_blocks(B + (int64_t)ct0 * KB, ntg * KB, tab, sB, spal);
     double ar[kMaxTG] = {}, ai[kMaxTG] = {};
     if constexpr (FORM == 2 || FORM == 4 || FORM == 5) {
         const int c0 = (int)(slice * slice_len);
         const int c1 = c0 + slice_len < tab.n_chunks ? (int)(c0 + slice_len) : tab.n_chunks;
-        if constexpr (FORM == 5) term_sum_segi_n<A>(sB, KB, ntg, tab, c0, c1, ar, ai);
+        if constexpr (FORM == 5) term_sum_segi_n<A>(sB, ntg, tab, c0, c1, ar, ai);
         else term_sum_seg<A, FORM == 4>(sB, KB, ntg, spal, tab, c0, c1, ar, ai);
     } else {
         const int64_t n0 = (int64_t)slice * slice_len;
@@ -1222,15 +1245,16 @@ __global__ __launch_bounds__(kCThreads) void contract_batch_kernel(const double2
     const BatchContractItem &it = items[w.item];
     const int KB = it.K * 792, ntg = w.ntg;
     double2 *spal = lds, *sB = lds + kMaxPalette;
-    stage_blocks(B + it.b_off + (int64_t)w.t0 * KB, ntg * KB, it.tab, sB, spal);
+    if (it.tab.seg_prefix && it.tab.coef_unit) stage_blocks_interleaved(B + it.b_off + (int64_t)w.t0 * KB, KB, ntg, sB);
+    else stage_blocks(B + it.b_off + (int64_t)w.t0 * KB, ntg * KB, it.tab, sB, spal);
     double ar[kMaxTG] = {}, ai[kMaxTG] = {};
     if (it.tab.seg_prefix) {
         const int c0 = (int)(w.slice * it.slice_len);
         const int c1 = c0 + it.slice_len < it.tab.n_chunks ? (int)(c0 + it.slice_len) : it.tab.n_chunks;
         switch (it.tab.coef_unit ? 10 + it.A : it.A * 2 + (it.tab.coef_real ? 1 : 0)) {
-        case 12: term_sum_segi_n<2>(sB, KB, ntg, it.tab, c0, c1, ar, ai); break;
-        case 13: term_sum_segi_n<3>(sB, KB, ntg, it.tab, c0, c1, ar, ai); break;
-        case 14: term_sum_segi_n<4>(sB, KB, ntg, it.tab, c0, c1, ar, ai); break;
+        case 12: term_sum_segi_n<2>(sB, ntg, it.tab, c0, c1, ar, ai); break;
+        case 13: term_sum_segi_n<3>(sB, ntg, it.tab, c0, c1, ar, ai); break;
+        case 14: term_sum_segi_n<4>(sB, ntg, it.tab, c0, c1, ar, ai); break;
         case 4: term_sum_seg<2, false>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
         case 5: term_sum_seg<2, true>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
         case 6: term_sum_seg<3, false>(sB, KB, ntg, spal, it.tab, c0, c1, ar, ai); break;
