@@ -298,9 +298,9 @@ __global__ __launch_bounds__(kStagedThreads) void blocks_f64_staged_kernel(
 //        (Gauss): with E = a + ib and Aop = c + id, K1 += (a + b) c,
 //        K2 += a (d - c), K3 += b (c + d), then Re = K1 - K3, Im = K1 + K2,
 //        formed once per workgroup after the site loop;
-//   P32: v_mfma_f32_16x16x4f32, the same three products with E, the sums
-//        a + b and d - c, c + d rounded to FP32 (complex64 entries are used
-//        as they are stored);
+//   P32: v_mfma_f32_16x16x4f32, four real MFMAs per complex product with E
+//        and Aop rounded to FP32 (complex64 entries are used as stored; the
+//        three-product form measured no faster here and doubled the error);
 //   PB3: v_mfma_f32_16x16x32_bf16, E and Aop split into two BF16 limbs
 //        (hi + lo), the three products hi*hi + hi*lo + lo*hi packed along K:
 //        one MFMA per real/imaginary output;
@@ -476,11 +476,11 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
     // end. |E'| stays within 2^+-kScaleSlack of the wave's largest entry, so no
     // product leaves the FP32 range for any propagator magnitude.
     constexpr int kNoScale = -100000, kScaleSlack = 24, kFoldBatches = 4, kExpBias = 2048;
-    f4 acc32[NT][3];  // P32: Gauss products K1, K2, K3; BF16 modes: Re, Im
+    f4 acc32[NT][2];  // FP32 sums of (Re, Im)
     int sc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        acc32[t][0] = acc32[t][1] = acc32[t][2] = f4{0, 0, 0, 0};
+        acc32[t][0] = acc32[t][1] = f4{0, 0, 0, 0};
         sc[t] = kNoScale;
     }
     int nfold = 0;
@@ -490,16 +490,10 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
             const double u = ldexp(1.0, sc[t]);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                if constexpr (MODE == WICK_P32) {
-                    const double k1 = acc32[t][0][v], k2 = acc32[t][1][v], k3 = acc32[t][2][v];
-                    acc[t][0][v] = fma(k1 - k3, u, acc[t][0][v]);
-                    acc[t][1][v] = fma(k1 + k2, u, acc[t][1][v]);
-                } else {
-                    acc[t][0][v] = fma((double)acc32[t][0][v], u, acc[t][0][v]);
-                    acc[t][1][v] = fma((double)acc32[t][1][v], u, acc[t][1][v]);
-                }
+                acc[t][0][v] = fma((double)acc32[t][0][v], u, acc[t][0][v]);
+                acc[t][1][v] = fma((double)acc32[t][1][v], u, acc[t][1][v]);
             }
-            acc32[t][0] = acc32[t][1] = acc32[t][2] = f4{0, 0, 0, 0};
+            acc32[t][0] = acc32[t][1] = f4{0, 0, 0, 0};
         }
     };
     // one staged batch: this wave's site quad against every group of the pass
@@ -592,31 +586,28 @@ __global__ __launch_bounds__(kNucThreads) void blocks_nucleon_kernel(
                             acc3[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey, v[t].x + v[t].y, acc3[t], 0, 0, 0);
                         }
                     } else if constexpr (MODE == WICK_P32) {
-                        // Gauss's three products in FP32: K1 += (a + b) c,
-                        // K2 += a (d - c), K3 += b (c + d) with E' = a + ib and
-                        // the S_f entry c + id (Re = K1 - K3, Im = K1 + K2 at the fold)
-                        const double exs = ex * fE, eys = ey * fE;
-                        const float fab = (float)(exs + eys), fa = (float)exs, fb = (float)eys;
-                        float vc[NT], vdc[NT], vcd[NT];
+                        // four real products in FP32 (Re += a c - b d, Im += a d + b c with
+                        // E' = a + ib and the S_f entry c + id); complex64 entries are
+                        // used as stored
+                        const float fa = (float)(ex * fE), fb = (float)(ey * fE);
+                        float vc[NT], vd[NT];
 #pragma unroll
                         for (int t = 0; t < NT; ++t) {
                             const TIn e = sfb[(tgroup[t] == g ? bo[t] : 0) + 12 * r];
-                            if constexpr (sizeof(TIn) == 8) {
-                                vc[t] = e.x;
-                                vdc[t] = e.y - e.x;
-                                vcd[t] = e.x + e.y;
-                            } else {
-                                vc[t] = (float)e.x;
-                                vdc[t] = (float)(e.y - e.x);
-                                vcd[t] = (float)(e.x + e.y);
-                            }
+                            vc[t] = (float)e.x;
+                            vd[t] = (float)e.y;
                         }
 #pragma unroll
                         for (int t = 0; t < NT; ++t) {
                             if (tgroup[t] != g) continue;
-                            acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fab, vc[t], acc32[t][0], 0, 0, 0);
-                            acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, vdc[t], acc32[t][1], 0, 0, 0);
-                            acc32[t][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb, vcd[t], acc32[t][2], 0, 0, 0);
+                            acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, vc[t], acc32[t][0], 0, 0, 0);
+                            acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, vd[t], acc32[t][1], 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) {
+                            if (tgroup[t] != g) continue;
+                            acc32[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(-fb, vd[t], acc32[t][0], 0, 0, 0);
+                            acc32[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb, vc[t], acc32[t][1], 0, 0, 0);
                         }
                     } else if constexpr (MODE == WICK_PB3) {
                         __bf16 xh, xl, yh, yl;
