@@ -176,7 +176,7 @@ struct SegTable {
     std::vector<uint64_t> words;
     std::vector<uint32_t> prefix;
     std::vector<int64_t> base;
-    std::vector<int32_t> len;
+    std::vector<int32_t> len;  // nodes per lane | (steps with a leaf 1) << 16
     std::vector<double2> pal;
     int seg_len = 0;
     int32_t unit = 0;  // integer-coefficient words (see TermTable) when nonzero
@@ -214,11 +214,13 @@ int32_t integer_unit(const wick_plan_s *p)
 // lanes of a half-wave in turn take, among their next kBalanceWindow words,
 // the one whose three groups are least used so far in that half-wave at that
 // step (balancing per quarter-wave instead measured 2 % slower on the
-// 64-configuration batch). Chunks are independent (host threads).
+// 64-configuration batch). A lane's two-leaf words (the first lane_two of
+// them) and its one-leaf words are reordered each among themselves, so the
+// two-leaf words stay ahead. Chunks are independent (host threads).
 int slices_per_group(int K, int64_t n_sets);
 constexpr int kBalanceWindow = 16;
 constexpr uint64_t kIdxMask = (1u << kPackBits) - 1;
-void balance_banks(SegTable &out, const std::vector<int32_t> &lane_len, int ntg)
+void balance_banks(SegTable &out, const std::vector<int32_t> &lane_len, const std::vector<int32_t> &lane_two, int ntg)
 {
     // LDS bank group of entry e: the term sum interleaves ntg slices, entry e of
     // slice 0 at 16-byte slot e * ntg (slice t adds t to every lane alike)
@@ -227,14 +229,14 @@ void balance_banks(SegTable &out, const std::vector<int32_t> &lane_len, int ntg)
     auto work = [&](size_t c_lo, size_t c_hi) {
         for (size_t c = c_lo; c < c_hi; ++c) {
             uint64_t *w = out.words.data() + out.base[c];
-            const int len = out.len[c];
-            const int32_t *ll = lane_len.data() + c * 64;
+            const int len = out.len[c] & 0xffff;
+            const int32_t *ll = lane_len.data() + c * 64, *l2 = lane_two.data() + c * 64;
             for (int j = 0; j < len; ++j)
                 for (int h = 0; h < 2; ++h) {
                     uint8_t cnt[3][16] = {};
                     for (int l = 32 * h; l < 32 * h + 32; ++l) {
                         if (j >= ll[l]) continue;
-                        const int end = std::min(ll[l], j + kBalanceWindow);
+                        const int end = std::min(j < l2[l] ? l2[l] : ll[l], j + kBalanceWindow);
                         int best = j, best_cost = 1 << 30;
                         for (int k = j; k < end; ++k) {
                             const uint64_t v = w[(size_t)k * 64 + l];
@@ -305,15 +307,23 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
     // segments: runs of nodes sharing the first A-2 indices, at most seg_nodes nodes
     const int seg_nodes = (int)std::min<size_t>(64, std::max<size_t>(8, nodes.size() / 65536));
     out.seg_len = seg_nodes * kNodeLeaves;
-    std::vector<std::pair<uint32_t, uint32_t>> segs;  // (first node, number of nodes)
+    struct Seg {
+        uint32_t first, n, two;  // first node, number of nodes, of them with two leaves
+    };
+    std::vector<Seg> segs;
     for (size_t i = 0; i < nodes.size();) {
         const uint32_t pre = prefix_of(ord[nodes[i].first]);
         size_t j = i + 1;
         while (j < nodes.size() && j - i < (size_t)seg_nodes && prefix_of(ord[nodes[j].first]) == pre) ++j;
-        segs.push_back({(uint32_t)i, (uint32_t)(j - i)});
+        uint32_t two = 0;
+        for (size_t q = i; q < j; ++q) two += nodes[q].second > 1;
+        segs.push_back({(uint32_t)i, (uint32_t)(j - i), two});
         i = j;
     }
-    std::stable_sort(segs.begin(), segs.end(), [](const auto &x, const auto &y) { return x.second > y.second; });
+    // longest segments first; among equal lengths, most two-leaf nodes first
+    // (so that the lanes of a chunk run out of leaf 1 at about the same step)
+    std::stable_sort(segs.begin(), segs.end(),
+                     [](const Seg &x, const Seg &y) { return x.n != y.n ? x.n > y.n : x.two > y.two; });
     const size_t n_chunks = (segs.size() + 63) / 64;
     out.prefix.assign(n_chunks * 64, 0);
     out.base.resize(n_chunks);
@@ -321,7 +331,7 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
     size_t total = 0;
     for (size_t c = 0; c < n_chunks; ++c) {
         out.base[c] = (int64_t)total;
-        out.len[c] = (int32_t)segs[c * 64].second;  // nodes per lane
+        out.len[c] = (int32_t)segs[c * 64].n;  // nodes per lane
         total += (size_t)out.len[c] * 64;  // one word per node
     }
     out.words.assign(total, 0);  // zero word: leaf 0, node 0, palette entry 0 (zero)
@@ -330,8 +340,10 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
             const size_t si = c * 64 + lane;
             if (si >= segs.size()) continue;  // an empty lane keeps zero words
             uint64_t *w = out.words.data() + out.base[c] + lane;
-            const uint32_t n0 = segs[si].first, nn = segs[si].second;
+            const uint32_t n0 = segs[si].first, nn = segs[si].n;
             out.prefix[si] = prefix_of(ord[nodes[n0].first]);
+            // integer words: the two-leaf nodes at steps [0, two), the others after
+            uint32_t at2 = 0, at1 = out.unit ? segs[si].two : 0;
             for (uint32_t kk = 0; kk < nn; ++kk) {
                 const auto &nd = nodes[n0 + kk];
                 const uint32_t t0 = ord[nd.first];
@@ -350,15 +362,30 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
                         v |= ((uint64_t)ix(A - 1, t1) << 36) | ((uint64_t)pidx[t1] << 50);
                     }
                 }
-                w[(size_t)kk * 64] = v;
+                const uint32_t at = !out.unit ? kk : nd.second > 1 ? at2++ : at1++;
+                w[(size_t)at * 64] = v;
             }
         }
     if (out.unit && !std::getenv("WICK_NO_BANK_BALANCE")) {
         // lengths of the lanes' segments, for the reordering below (the
         // variable turns it off, for measurement)
-        std::vector<int32_t> lane_len(n_chunks * 64, 0);
-        for (size_t si = 0; si < segs.size(); ++si) lane_len[si] = (int32_t)segs[si].second;
-        balance_banks(out, lane_len, slices_per_group((int)p->kinds.size(), kMaxTG));
+        std::vector<int32_t> lane_len(n_chunks * 64, 0), lane_two(n_chunks * 64, 0);
+        for (size_t si = 0; si < segs.size(); ++si) {
+            lane_len[si] = (int32_t)segs[si].n;
+            lane_two[si] = (int32_t)segs[si].two;
+        }
+        balance_banks(out, lane_len, lane_two, slices_per_group((int)p->kinds.size(), kMaxTG));
+    }
+    // steps in which some lane's word has a leaf 1: all of them in the
+    // palette form, the lanes' largest number of two-leaf nodes otherwise
+    for (size_t c = 0; c < n_chunks; ++c) {
+        int32_t two = out.len[c];
+        if (out.unit) {
+            two = 0;
+            for (size_t si = c * 64; si < std::min(segs.size(), c * 64 + 64); ++si)
+                two = std::max(two, (int32_t)segs[si].two);
+        }
+        out.len[c] |= two << 16;
     }
     return true;
 }

@@ -24,6 +24,7 @@
 // shuffle/LDS tree reduces the workgroup and a second kernel sums the slices
 // in order.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -975,7 +976,7 @@ __device__ __forceinline__ void term_sum_seg(const double2 *__restrict__ sB, int
             }
         }
         const uint64_t *wp = tab.words + tab.chunk_base[c] + lane;
-        const int nodes = tab.chunk_len[c];  // uniform over the wave
+        const int nodes = tab.chunk_len[c] & 0xffff;  // uniform over the wave
         uint64_t cur[kPrefetch], nxt[kPrefetch] = {};
         auto fetch = [&](int k0, uint64_t (&w)[kPrefetch]) {
 #pragma unroll
@@ -1028,51 +1029,72 @@ __device__ __forceinline__ void term_sum_seg(const double2 *__restrict__ sB, int
 // that the gathers of every slice are issued together and one wait covers
 // them). The slices' blocks are interleaved in LDS, entry e of slice s at
 // sB[e * NTG + s] (stage_blocks_interleaved), so the NTG gathers of one entry
-// share one address and differ by an immediate offset. A missing leaf (q = 0)
-// and a padding word read entry 0 and weigh it by zero; lanes reading one
-// address share the read. The coefficients are the integers q; the table's
-// unit multiplies each segment's sum once.
+// share one address and differ by an immediate offset. The first `two` steps
+// of a chunk gather both leaves of each lane's word (a missing leaf 1, q = 0,
+// reads entry 0 and weighs it by zero; lanes reading one address share the
+// read); in the later steps no lane's word has a leaf 1 and its gather is
+// skipped, a branch taken by the whole wave. A padding word reads entry 0 with
+// weight zero. The coefficients are the integers q; the table's unit
+// multiplies each segment's sum once. Chunk index, length and base are the
+// same for the whole wave and held in scalar registers, so the loop control
+// and the word addresses cost no vector instructions.
 template <int A, int NTG>
 __device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, const TermTable &tab, int c0, int c1,
                                               double (&ar)[kMaxTG], double (&ai)[kMaxTG])
 {
     constexpr uint32_t kMask = (1u << kPackBits) - 1;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    c0 = __builtin_amdgcn_readfirstlane(c0);
+    c1 = __builtin_amdgcn_readfirstlane(c1);
     const double unit = (double)tab.coef_unit;
     for (int c = c0 + wave; c < c1; c += kCThreads / 64) {
         const uint32_t pre = tab.seg_prefix[(int64_t)c * 64 + lane];
         double sx[NTG], sy[NTG];
 #pragma unroll
         for (int tg = 0; tg < NTG; ++tg) sx[tg] = sy[tg] = 0.0;
+        const int cl = __builtin_amdgcn_readfirstlane(tab.chunk_len[c]);
+        const int nodes = cl & 0xffff, two = cl >> 16;
         const uint64_t *wp = tab.words + tab.chunk_base[c] + lane;
-        const int nodes = tab.chunk_len[c];  // uniform over the wave
-        auto eval = [&](uint64_t w) {
+        auto eval = [&](uint64_t w, auto leaf1) {
+            constexpr bool kLeaf1 = decltype(leaf1)::value;
             const double2 *pn = sB + (int)((w >> kPackBits) & kMask) * NTG;
             const double2 *p0 = sB + (int)(w & kMask) * NTG;
-            const double2 *p1 = sB + (int)((w >> (2 * kPackBits)) & kMask) * NTG;
             // q of leaf 0 is bits [42, 53) and q of leaf 1 bits [53, 64) of the
             // word: bits [10, 21) and [21, 32) of its high half (32-bit
             // arithmetic shifts sign-extend them)
             const uint32_t hi = (uint32_t)(w >> 32);
             const double cf0 = (double)((int)(hi << 11) >> 21);
-            const double cf1 = (double)((int)hi >> 21);
             double2 b0[NTG], b1[NTG], bn[NTG];
 #pragma unroll
             for (int tg = 0; tg < NTG; ++tg) {
                 bn[tg] = pn[tg];
                 b0[tg] = p0[tg];
-                b1[tg] = p1[tg];
+            }
+            if constexpr (kLeaf1) {
+                const double2 *p1 = sB + (int)((w >> (2 * kPackBits)) & kMask) * NTG;
+#pragma unroll
+                for (int tg = 0; tg < NTG; ++tg) b1[tg] = p1[tg];
             }
 #pragma unroll
             for (int tg = 0; tg < NTG; ++tg) {
-                const double s3x = fma(cf1, b1[tg].x, cf0 * b0[tg].x);
-                const double s3y = fma(cf1, b1[tg].y, cf0 * b0[tg].y);
+                double s3x, s3y;
+                if constexpr (kLeaf1) {
+                    const double cf1 = (double)((int)hi >> 21);
+                    s3x = fma(cf1, b1[tg].x, cf0 * b0[tg].x);
+                    s3y = fma(cf1, b1[tg].y, cf0 * b0[tg].y);
+                } else {
+                    s3x = cf0 * b0[tg].x;
+                    s3y = cf0 * b0[tg].y;
+                }
                 sx[tg] = fma(bn[tg].x, s3x, sx[tg]);
                 sx[tg] = fma(-bn[tg].y, s3y, sx[tg]);
                 sy[tg] = fma(bn[tg].x, s3y, sy[tg]);
                 sy[tg] = fma(bn[tg].y, s3x, sy[tg]);
             }
         };
+        constexpr std::true_type kBoth{};
+        constexpr std::false_type kLeaf0{};
         // the words of the next kPrefetch nodes are loaded while the current
         // ones are evaluated (indices clamped into the chunk: always valid)
         uint64_t cur[kPrefetch], nxt[kPrefetch];
@@ -1083,11 +1105,18 @@ __device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, co
         if (nodes > 0) fetch(0, cur);
         for (int k0 = 0; k0 < nodes; k0 += kPrefetch) {
             if (k0 + kPrefetch < nodes) fetch(k0 + kPrefetch, nxt);
-            if (k0 + kPrefetch <= nodes) {
+            if (k0 + kPrefetch <= two) {
 #pragma unroll
-                for (int u = 0; u < kPrefetch; ++u) eval(cur[u]);
-            } else {
-                for (int u = 0; u < nodes - k0; ++u) eval(cur[u]);
+                for (int u = 0; u < kPrefetch; ++u) eval(cur[u], kBoth);
+            } else if (k0 >= two && k0 + kPrefetch <= nodes) {
+#pragma unroll
+                for (int u = 0; u < kPrefetch; ++u) eval(cur[u], kLeaf0);
+            } else {  // the steps where leaf 1 ends, or the chunk's last steps
+#pragma unroll
+                for (int u = 0; u < kPrefetch; ++u) {
+                    if (k0 + u < two) eval(cur[u], kBoth);
+                    else if (k0 + u < nodes) eval(cur[u], kLeaf0);
+                }
             }
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u) cur[u] = nxt[u];

@@ -92,19 +92,22 @@ constexpr int kMaxPalette = 256;
 // so every term costs one LDS gather and every node one more, instead of A
 // per term; as every node is one word the lanes of a wave never diverge.
 // Segments are sorted by length and dealt to the 64 lanes of a chunk; chunk
-// c holds chunk_len[c] nodes per lane, interleaved (node j of lane l at
-// chunk_base[c] + 64 j + l), shorter segments padded with zero words. Node
-// word bits: leaf 0 [0,14), node index [14,28), palette index of leaf 0
-// [28,36), leaf 1 [36,50), palette index of leaf 1 [50,58); palette entry 0
-// is zero.
+// c holds L = chunk_len[c] & 0xffff nodes per lane, interleaved (node j of
+// lane l at chunk_base[c] + 64 j + l), shorter segments padded with zero
+// words. Node word bits: leaf 0 [0,14), node index [14,28), palette index of
+// leaf 0 [28,36), leaf 1 [36,50), palette index of leaf 1 [50,58); palette
+// entry 0 is zero.
 //
 // Integer-coefficient words (coef_unit != 0: every coefficient is a real
 // integer multiple q * coef_unit with |q| <= 1023, true of every built-in
 // nucleus): leaf 0 [0,14), node index [14,28), leaf 1 [28,42), q of leaf 0
 // [42,53) and q of leaf 1 [53,64), both two's complement. The coefficient
 // is formed in registers (q * coef_unit is an exact integer), so no palette
-// is read from LDS; q = 0 marks a missing leaf (its gather is skipped), and
-// a word with q of leaf 0 equal to 0 is padding (no gather at all).
+// is read from LDS. q = 0 marks a missing leaf (index 0, weight zero) and a
+// zero word is padding. Segments of equal length are sorted by their number
+// of two-leaf nodes, and each lane holds its two-leaf nodes first, so a
+// chunk's steps j >= chunk_len[c] >> 16 have no leaf 1 in any lane and the
+// term sum skips that gather there.
 constexpr int kNodeLeaves = 2;
 constexpr int kIntCoefMax = 1023;
 struct TermTable {
@@ -117,7 +120,7 @@ struct TermTable {
     // segmented form (seg_prefix != null)
     const uint32_t *seg_prefix;  // [n_chunks * 64]: A-2 indices of 14 bits
     const int64_t *chunk_base;   // [n_chunks]
-    const int32_t *chunk_len;    // [n_chunks]
+    const int32_t *chunk_len;    // [n_chunks]: nodes per lane, plus (steps with a leaf 1) << 16
     int32_t n_chunks;
     int32_t coef_unit;           // segmented form: 0 palette words, else integer-coefficient words
 };
