@@ -77,6 +77,23 @@ KINDS = {"2H": 4, "3He": 9, "3H": 9, "4He": 4}
 EROWS = {"2H": [4], "3He": [2, 2], "3H": [2, 2], "4He": [4]}
 
 
+def sum_flops_per_slice(plan):
+    """FP64 flops of the term-sum kernel per time slice, from the plan's table
+    (wick_plan_sum_work): 6A + 2 per term for the per-term forms; for the word
+    forms 14 per two-leaf word (q0 b0 + q1 b1 with real q: 6, the complex
+    multiply-add by the node entry: 8) and 10 per one-leaf word, plus per
+    segment the complex product by its prefix (6 per prefix entry) or, in the
+    factored form, by unit * G (2), and the complex multiply-add into the sum
+    (8). A complex palette coefficient adds 8 flops per gathered leaf."""
+    w = plan.sum_work()
+    A = plan.A
+    if w["form"] in ("plain", "packed"):
+        return plan.n_terms * (6 * A + 2)
+    per_seg = 10 if w["form"] == "factored" else 6 * (A - 2) + 8
+    per2, per1 = (14, 10) if w["form"] != "segmented-palette" else (30, 18)
+    return per2 * w["words2"] + per1 * w["words1"] + per_seg * w["segments"]
+
+
 def gemm_flops_per_site(nucleus, kinds=None):
     """The MFMA contraction: 12 rows (i1) per kind x 144 columns x 3 E rows x 8
     flops per complex multiply-add (counted as written, whatever the number of
@@ -218,6 +235,7 @@ def main():
         note(f"{p}: {runs[p]['ms_per_step']:.3f} ms/step")
 
     n_term_evals = sum(plans[n].n_terms * T for n, _ in items)
+    slice_flops = {n: sum_flops_per_slice(plans[n]) for n in plans}
     traffic = load_traffic(args.workload)
 
     def rooflines(p, r):
@@ -228,9 +246,9 @@ def main():
         gemm = sum(gemm_flops_per_site(n) * V * T for n, _ in items)
         erow = sum(erow_flops_per_site(n) * V * T for n, _ in items)
         tf_b = gemm / (avg_b * 1e-3) / 1e12
-        # term sum: 6A + 2 FP64 flops per term and time slice, FP64 vector ALU peak
-        # (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s)
-        sum_flops = sum(plans[n].n_terms * T * (6 * plans[n].A + 2) for n, _ in items)
+        # term sum: the flops of the table's words per time slice (sum_flops_per_slice),
+        # FP64 vector ALU peak (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s)
+        sum_flops = sum(slice_flops[n] * T for n, _ in items)
         tf_c = sum_flops / (avg_c * 1e-3) / 1e12 if nc else 0.0
         tr = traffic.get(p, {})
         rb = {"bound": "mfma", "kernel": "blocks_nucleon_kernel", "achieved": tf_b, "peak": PEAK_TFLOPS[p],
@@ -661,9 +679,10 @@ def point_bench(args):
         nc, msc = W.profile_read("contract")
         A, K, N = pl.info()
         nw = sum(len(pl.kind(k)[1]) for k in range(K))
-        # per site: 28 flops per (block entry, weight) of the block build, 6A + 2 per term
+        # per site: 28 flops per (block entry, weight) of the block build; the term
+        # sum's flops per slice from its table (sum_flops_per_slice)
         tf_b = 792 * nw * 28 * slots / (msb / args.steps * 1e-3) / 1e12
-        tf_c = N * (6 * A + 2) * slots / (msc / args.steps * 1e-3) / 1e12
+        tf_c = sum_flops_per_slice(pl) * slots / (msc / args.steps * 1e-3) / 1e12
         cb, cd = Cb.cpu().numpy()[0], C.cpu().numpy()[0]
         dev = np.max(np.abs((cb[:, 0] - cd[:, 0]) + 1j * (cb[:, 1] - cd[:, 1])) / np.abs(cd[:, 0] + 1j * cd[:, 1]))
         out["block_form"] = {"ms_per_step": 1e3 * dtb, "s_per_time_slice": dtb / T, "speedup_vs_determinants": step_s / dtb,

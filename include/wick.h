@@ -134,6 +134,19 @@ wick_status wick_plan_info(wick_plan_t plan, int32_t *A, int32_t *n_kinds, int64
 wick_status wick_plan_stats(wick_plan_t plan, int64_t *n_enumerated, int64_t *n_groups,
                             int64_t *n_terms, double *false_merge_bound);
 
+/* Work of the plan's term sum per time slice, for pricing the term-sum
+ * kernel (Eq. 2.9's signed sum over the deduplicated table, Sec. 3.2). form:
+ * 0 plain, 1 packed (one word per term), 2 segmented with a coefficient
+ * palette, 3 segmented with integer coefficients, 4 factored (A = 4: each
+ * list of terms shared by several index prefixes is summed once and
+ * weighted by the sum of its prefix products); words2 / words1: table words
+ * gathering two leaves / one leaf (padding not counted; for forms 0 and 1,
+ * words1 = n_terms); segments: lanes holding a segment (forms 2-4). Builds
+ * the table on the host when the plan has not been used on a device yet
+ * (seconds for 4He). Any output pointer may be NULL. */
+wick_status wick_plan_sum_work(wick_plan_t plan, int32_t *form, int64_t *words2, int64_t *words1,
+                               int64_t *segments);
+
 /* Copy the table out (host arrays): kidx[A][n_terms] with
  * kidx = kind*792 + c, and coef[n_terms][2] (scale included). */
 wick_status wick_plan_table(wick_plan_t plan, uint16_t *kidx, double *coef);

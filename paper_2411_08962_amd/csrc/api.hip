@@ -16,6 +16,7 @@
 #include <sstream>
 #include <string>
 #include <tuple>
+#include <unordered_map>
 #include <vector>
 
 #include "kernels.hpp"
@@ -124,6 +125,7 @@ struct DevPlan {
     uint32_t *seg_prefix = nullptr;  // segmented table only
     int64_t *chunk_base = nullptr;
     int32_t *chunk_len = nullptr;
+    int32_t *chunk_g = nullptr;  // factored table only
     int n_chunks = 0, seg_len = 0;
     int coef_unit = 0;  // segmented table: integer-coefficient words when nonzero
 };
@@ -141,6 +143,7 @@ TermTable table_of(const DevPlan *d, const wick_plan_s *p)
     t.coef_unit = d->coef_unit;
     t.chunk_base = d->chunk_base;
     t.chunk_len = d->chunk_len;
+    t.chunk_g = d->chunk_g;
     t.n_chunks = d->n_chunks;
     return t;
 }
@@ -177,6 +180,7 @@ struct SegTable {
     std::vector<uint32_t> prefix;
     std::vector<int64_t> base;
     std::vector<int32_t> len;  // nodes per lane | (steps with a leaf 1) << 16
+    std::vector<int32_t> g;    // factored form: steps of prefix-group words per chunk (else empty)
     std::vector<double2> pal;
     int seg_len = 0;
     int32_t unit = 0;  // integer-coefficient words (see TermTable) when nonzero
@@ -209,18 +213,21 @@ int32_t integer_unit(const wick_plan_s *p)
 // hit the same group (measured on MI355X: 13.5 cycles per wave-wide read for
 // random slots; 9.3 when each group is hit at most twice per half-wave or per
 // quarter-wave; 6.3 when in addition every quarter-wave uses the same
-// lane-to-group pattern). The sum of a segment does not depend on the order
-// of its words, so each lane's words are reordered greedily: at each step the
-// lanes of a half-wave in turn take, among their next kBalanceWindow words,
-// the one whose three groups are least used so far in that half-wave at that
-// step (balancing per quarter-wave instead measured 2 % slower on the
-// 64-configuration batch). A lane's two-leaf words (the first lane_two of
-// them) and its one-leaf words are reordered each among themselves, so the
-// two-leaf words stay ahead. Chunks are independent (host threads).
+// lane-to-group pattern). A sum does not depend on the order of its words,
+// so each lane's words are reordered greedily: at each step the lanes of a
+// half-wave in turn take, among their next kBalanceWindow words, the one
+// whose three groups are least used so far in that half-wave at that step
+// (balancing per quarter-wave instead measured 2 % slower on the
+// 64-configuration batch). A lane's words fall into parts that are reordered
+// each among themselves: its prefix-group words (steps [0, lane_g), factored
+// form only), then, from the chunk's step G = g[c] (0 unless factored), its
+// two-leaf words (lane_two of them) and its one-leaf words (lane_len in all).
+// Chunks are independent (host threads).
 int slices_per_group(int K, int64_t n_sets);
 constexpr int kBalanceWindow = 16;
 constexpr uint64_t kIdxMask = (1u << kPackBits) - 1;
-void balance_banks(SegTable &out, const std::vector<int32_t> &lane_len, const std::vector<int32_t> &lane_two, int ntg)
+void balance_banks(SegTable &out, const std::vector<int32_t> &lane_len, const std::vector<int32_t> &lane_two,
+                   const std::vector<int32_t> &lane_g, int ntg)
 {
     // LDS bank group of entry e: the term sum interleaves ntg slices, entry e of
     // slice 0 at 16-byte slot e * ntg (slice t adds t to every lane alike)
@@ -229,14 +236,23 @@ void balance_banks(SegTable &out, const std::vector<int32_t> &lane_len, const st
     auto work = [&](size_t c_lo, size_t c_hi) {
         for (size_t c = c_lo; c < c_hi; ++c) {
             uint64_t *w = out.words.data() + out.base[c];
-            const int len = out.len[c] & 0xffff;
+            const int len = out.len[c] & 0xffff, G = out.g.empty() ? 0 : out.g[c];
             const int32_t *ll = lane_len.data() + c * 64, *l2 = lane_two.data() + c * 64;
+            const int32_t *lg = lane_g.empty() ? nullptr : lane_g.data() + c * 64;
             for (int j = 0; j < len; ++j)
                 for (int h = 0; h < 2; ++h) {
                     uint8_t cnt[3][16] = {};
                     for (int l = 32 * h; l < 32 * h + 32; ++l) {
-                        if (j >= ll[l]) continue;
-                        const int end = std::min(j < l2[l] ? l2[l] : ll[l], j + kBalanceWindow);
+                        int part_end;  // end of the part holding step j (exclusive)
+                        if (j < G) {
+                            if (j >= lg[l]) continue;
+                            part_end = lg[l];
+                        } else {
+                            const int jm = j - G;
+                            if (jm >= ll[l]) continue;
+                            part_end = G + (jm < l2[l] ? l2[l] : ll[l]);
+                        }
+                        const int end = std::min(part_end, j + kBalanceWindow);
                         int best = j, best_cost = 1 << 30;
                         for (int k = j; k < end; ++k) {
                             const uint64_t v = w[(size_t)k * 64 + l];
@@ -265,10 +281,13 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
     const int A = p->A;
     const size_t nt = (size_t)p->n_terms;
     if (A < 2 || A > 4 || (int)p->kinds.size() > kMaxLdsKinds || nt == 0 || nt > 0xffffffffULL) return false;
+    out = SegTable{};
     std::vector<uint8_t> pidx;
     if (!palette_of(p, true, pidx, out.pal)) return false;
+    // integer words for A <= 3 (an A = 4 table with integer coefficients
+    // takes the factored form, which sets chunk_g)
     const char *form_env = std::getenv("WICK_TABLE_FORM");
-    out.unit = form_env && std::string(form_env) == "segmented-palette" ? 0 : integer_unit(p);
+    out.unit = (form_env && std::string(form_env) == "segmented-palette") || A == 4 ? 0 : integer_unit(p);
     auto qbits = [&](uint32_t t) {  // 11-bit two's complement of coef / unit
         const int64_t q = (int64_t)(p->coef_re[t] / out.unit);
         return (uint64_t)q & 0x7ff;
@@ -374,7 +393,7 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
             lane_len[si] = (int32_t)segs[si].n;
             lane_two[si] = (int32_t)segs[si].two;
         }
-        balance_banks(out, lane_len, lane_two, slices_per_group((int)p->kinds.size(), kMaxTG));
+        balance_banks(out, lane_len, lane_two, {}, slices_per_group((int)p->kinds.size(), kMaxTG));
     }
     // steps in which some lane's word has a leaf 1: all of them in the
     // palette form, the lanes' largest number of two-leaf nodes otherwise
@@ -387,6 +406,233 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
         }
         out.len[c] |= two << 16;
     }
+    return true;
+}
+
+// Factored form of an A = 4 table with integer coefficients (see TermTable).
+// The index positions are reordered so that the pair of positions with the
+// fewest distinct index pairs comes first: the prefix (i, j) of a term. The
+// terms of one prefix, sorted by their last two indices and divided by g, the
+// gcd of their q with the sign of the first, are the prefix's list; prefixes
+// with equal lists share it, so that
+//   C = unit * sum_m G_m M_m,  M_m = sum over the words of list m of
+//   B[node] (q0 B[leaf0] + q1 B[leaf1]),  G_m = sum over the prefixes of
+//   list m of g B[i] B[j],
+// where the G words pair the prefixes of one i as node i with leaves j. This
+// evaluates each list once for all its prefixes (4He: 28751 lists for 364752
+// prefixes). Each list's words (two-leaf words first) are cut into pieces of
+// at most kPieceWords; a piece is one lane's segment and carries all the G
+// words of its list. Pieces are sorted by length, then by their two-leaf
+// words, and dealt to the 64 lanes of a chunk; chunk c holds g[c] steps of G
+// words (fewer in a lane padded with zero words), then its list words.
+constexpr int kPieceWords = 64;
+bool factor_table(const wick_plan_s *p, SegTable &out)
+{
+    const size_t nt = (size_t)p->n_terms;
+    if (p->A != 4 || (int)p->kinds.size() > kMaxLdsKinds || nt == 0 || nt > 0xffffffffULL) return false;
+    const char *form_env = std::getenv("WICK_TABLE_FORM");
+    if (form_env && std::string(form_env) == "segmented-palette") return false;
+    out.unit = integer_unit(p);
+    if (!out.unit) return false;
+    out.pal.assign(1, double2{0.0, 0.0});  // not read by integer words
+    const uint16_t *k = p->kidx.data();
+    // the leading pair of positions: fewest distinct index pairs (a bitmap of
+    // 2^28 pairs per candidate, candidates on host threads)
+    int perm[4] = {0, 1, 2, 3};
+    {
+        const int cand[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+        size_t count[6] = {};
+        auto distinct = [&](int i) {
+            std::vector<uint64_t> bits((size_t)1 << (2 * kPackBits - 6), 0);
+            const uint16_t *ka = k + (size_t)cand[i][0] * nt, *kb = k + (size_t)cand[i][1] * nt;
+            for (size_t t = 0; t < nt; ++t) {
+                const uint32_t key = ((uint32_t)ka[t] << kPackBits) | kb[t];
+                bits[key >> 6] |= (uint64_t)1 << (key & 63);
+            }
+            size_t n = 0;
+            for (uint64_t b : bits) n += (size_t)__builtin_popcountll(b);
+            count[i] = n;
+        };
+        std::vector<std::thread> th;
+        for (int i = 0; i < 6; ++i) th.emplace_back(distinct, i);
+        for (auto &t : th) t.join();
+        int best = 0;
+        for (int i = 1; i < 6; ++i)
+            if (count[i] < count[best]) best = i;
+        perm[0] = cand[best][0];
+        perm[1] = cand[best][1];
+        for (int a = 0, o = 2; a < 4; ++a)
+            if (a != perm[0] && a != perm[1]) perm[o++] = a;
+    }
+    auto ix = [&](int a, uint32_t t) { return (uint32_t)k[(size_t)perm[a] * nt + t]; };
+    auto qv = [&](uint32_t t) { return (int32_t)(p->coef_re[t] / out.unit); };
+    // terms in lexicographic order of their reordered index tuples
+    std::vector<uint32_t> ord(nt), tmp(nt);
+    for (size_t t = 0; t < nt; ++t) ord[t] = (uint32_t)t;
+    {
+        std::vector<size_t> cnt((size_t)1 << kPackBits);
+        for (int a = 3; a >= 0; --a) {
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (size_t i = 0; i < nt; ++i) ++cnt[ix(a, ord[i])];
+            size_t acc = 0;
+            for (auto &c : cnt) { const size_t v = c; c = acc; acc += v; }
+            for (size_t i = 0; i < nt; ++i) tmp[cnt[ix(a, ord[i])]++] = ord[i];
+            ord.swap(tmp);
+        }
+    }
+    tmp.clear();
+    tmp.shrink_to_fit();
+    // prefixes: runs [i0, i1) of ord sharing the first two indices, with g
+    struct Prefix {
+        uint32_t i0, i1;
+        int32_t g;
+    };
+    std::vector<Prefix> pre;
+    for (size_t i = 0; i < nt;) {
+        const uint32_t a0 = ix(0, ord[i]), a1 = ix(1, ord[i]);
+        size_t j = i + 1;
+        while (j < nt && ix(0, ord[j]) == a0 && ix(1, ord[j]) == a1) ++j;
+        int32_t g = 0;
+        for (size_t n = i; n < j; ++n) {
+            int32_t a = std::abs(qv(ord[n])), b = g;
+            while (b) { const int32_t r = a % b; a = b; b = r; }
+            g = a;
+        }
+        if (qv(ord[i]) < 0) g = -g;
+        pre.push_back({(uint32_t)i, (uint32_t)j, g});
+        i = j;
+    }
+    // distinct lists (hash of (node, leaf, q / g) over the run, equality checked)
+    auto list_hash = [&](const Prefix &x) {
+        uint64_t h = 0x9e3779b97f4a7c15ULL ^ (uint64_t)(x.i1 - x.i0);
+        for (uint32_t n = x.i0; n < x.i1; ++n) {
+            const uint32_t t = ord[n];
+            const uint64_t v = ((uint64_t)ix(2, t) << 32) | ((uint64_t)ix(3, t) << 11) | (uint64_t)((qv(t) / x.g) & 0x7ff);
+            h = (h ^ v) * 0x100000001b3ULL;
+            h ^= h >> 29;
+        }
+        return h;
+    };
+    auto same_list = [&](const Prefix &x, const Prefix &y) {
+        if (x.i1 - x.i0 != y.i1 - y.i0) return false;
+        for (uint32_t n = 0; n < x.i1 - x.i0; ++n) {
+            const uint32_t t = ord[x.i0 + n], u = ord[y.i0 + n];
+            if (ix(2, t) != ix(2, u) || ix(3, t) != ix(3, u) || qv(t) / x.g != qv(u) / y.g) return false;
+        }
+        return true;
+    };
+    std::unordered_map<uint64_t, std::vector<uint32_t>> by_hash;  // hash -> lists
+    std::vector<uint32_t> rep;                                    // list -> its first prefix
+    std::vector<std::vector<uint32_t>> members;                   // list -> its prefixes
+    for (uint32_t pi = 0; pi < (uint32_t)pre.size(); ++pi) {
+        auto &cands = by_hash[list_hash(pre[pi])];
+        uint32_t m = UINT32_MAX;
+        for (uint32_t c : cands)
+            if (same_list(pre[rep[c]], pre[pi])) { m = c; break; }
+        if (m == UINT32_MAX) {
+            m = (uint32_t)rep.size();
+            rep.push_back(pi);
+            members.emplace_back();
+            cands.push_back(m);
+        }
+        members[m].push_back(pi);
+    }
+    auto word = [](uint32_t node, uint32_t l0, int32_t q0, uint32_t l1, int32_t q1) {
+        return (uint64_t)l0 | ((uint64_t)node << kPackBits) | ((uint64_t)l1 << (2 * kPackBits)) |
+               ((uint64_t)((uint32_t)q0 & 0x7ff) << 42) | ((uint64_t)((uint32_t)q1 & 0x7ff) << 53);
+    };
+    // words of each list: list words (two-leaf first) and G words
+    const size_t n_lists = rep.size();
+    std::vector<size_t> mw_off(n_lists + 1, 0), gw_off(n_lists + 1, 0);
+    std::vector<uint32_t> mw_two(n_lists, 0);
+    std::vector<uint64_t> mw, gw;
+    for (size_t m = 0; m < n_lists; ++m) {
+        const Prefix &x = pre[rep[m]];
+        std::vector<uint64_t> one;
+        for (uint32_t n = x.i0; n < x.i1;) {
+            const uint32_t node = ix(2, ord[n]);
+            uint32_t e = n + 1;
+            while (e < x.i1 && ix(2, ord[e]) == node) ++e;
+            for (uint32_t a = n; a < e; a += 2) {
+                const uint32_t t0 = ord[a];
+                if (a + 1 < e) {
+                    const uint32_t t1 = ord[a + 1];
+                    mw.push_back(word(node, ix(3, t0), qv(t0) / x.g, ix(3, t1), qv(t1) / x.g));
+                    ++mw_two[m];
+                } else {
+                    one.push_back(word(node, ix(3, t0), qv(t0) / x.g, 0, 0));
+                }
+            }
+            n = e;
+        }
+        mw.insert(mw.end(), one.begin(), one.end());
+        mw_off[m + 1] = mw.size();
+        const auto &mem = members[m];  // prefixes in lexicographic order
+        for (size_t a = 0; a < mem.size();) {
+            const Prefix &y = pre[mem[a]];
+            const uint32_t i = ix(0, ord[y.i0]);
+            if (a + 1 < mem.size() && ix(0, ord[pre[mem[a + 1]].i0]) == i) {
+                const Prefix &z = pre[mem[a + 1]];
+                gw.push_back(word(i, ix(1, ord[y.i0]), y.g, ix(1, ord[z.i0]), z.g));
+                a += 2;
+            } else {
+                gw.push_back(word(i, ix(1, ord[y.i0]), y.g, 0, 0));
+                a += 1;
+            }
+        }
+        gw_off[m + 1] = gw.size();
+    }
+    // pieces: (list, first list word, words, two-leaf words)
+    struct Piece {
+        uint32_t m, w0, n, two;
+    };
+    std::vector<Piece> pieces;
+    for (size_t m = 0; m < n_lists; ++m) {
+        const uint32_t n = (uint32_t)(mw_off[m + 1] - mw_off[m]);
+        for (uint32_t a = 0; a < n; a += kPieceWords) {
+            const uint32_t len = std::min<uint32_t>(kPieceWords, n - a);
+            const uint32_t two = a < mw_two[m] ? std::min<uint32_t>(len, mw_two[m] - a) : 0;
+            pieces.push_back({(uint32_t)m, (uint32_t)mw_off[m] + a, len, two});
+        }
+    }
+    std::stable_sort(pieces.begin(), pieces.end(),
+                     [](const Piece &x, const Piece &y) { return x.n != y.n ? x.n > y.n : x.two > y.two; });
+    const size_t n_chunks = (pieces.size() + 63) / 64;
+    out.prefix.assign(n_chunks * 64, 0);
+    out.base.resize(n_chunks);
+    out.len.resize(n_chunks);
+    out.g.resize(n_chunks);
+    std::vector<int32_t> lane_len(n_chunks * 64, 0), lane_two(n_chunks * 64, 0), lane_g(n_chunks * 64, 0);
+    size_t total = 0;
+    for (size_t c = 0; c < n_chunks; ++c) {
+        int32_t G = 0, M = 0, two = 0;
+        for (size_t si = c * 64; si < std::min(pieces.size(), c * 64 + 64); ++si) {
+            const Piece &pc = pieces[si];
+            lane_g[si] = (int32_t)(gw_off[pc.m + 1] - gw_off[pc.m]);
+            lane_len[si] = (int32_t)pc.n;
+            lane_two[si] = (int32_t)pc.two;
+            G = std::max(G, lane_g[si]);
+            M = std::max(M, lane_len[si]);
+            two = std::max(two, lane_two[si]);
+        }
+        if (G + M > 0xffff) return false;
+        out.base[c] = (int64_t)total;
+        out.g[c] = G;
+        out.len[c] = (G + M) | ((G + two) << 16);
+        total += (size_t)(G + M) * 64;
+    }
+    out.words.assign(total, 0);
+    for (size_t si = 0; si < pieces.size(); ++si) {
+        const size_t c = si / 64, lane = si % 64;
+        uint64_t *w = out.words.data() + out.base[c] + lane;
+        const Piece &pc = pieces[si];
+        for (int32_t a = 0; a < lane_g[si]; ++a) w[(size_t)a * 64] = gw[gw_off[pc.m] + a];
+        for (uint32_t a = 0; a < pc.n; ++a) w[(size_t)(out.g[c] + a) * 64] = mw[pc.w0 + a];
+    }
+    // terms per lane and chunk, for sizing the term-sum workgroups
+    out.seg_len = (int)std::max<size_t>(1, nt / (64 * n_chunks));
+    if (!std::getenv("WICK_NO_BANK_BALANCE"))
+        balance_banks(out, lane_len, lane_two, lane_g, slices_per_group((int)p->kinds.size(), kMaxTG));
     return true;
 }
 
@@ -419,6 +665,86 @@ bool pack_table(const wick_plan_s *p, std::vector<uint64_t> &words, std::vector<
 
 std::mutex g_dev_mu;
 std::map<const wick_plan_s *, std::deque<DevPlan>> g_dev;  // deque: stable element addresses
+
+// Form of a plan's term table (the values of wick_plan_sum_work's form).
+enum TableForm { kFormPlain = 0, kFormPacked = 1, kFormSegPalette = 2, kFormSegInt = 3, kFormFactored = 4 };
+bool segment_table(const wick_plan_s *p, SegTable &out);
+bool factor_table(const wick_plan_s *p, SegTable &out);
+bool pack_table(const wick_plan_s *p, std::vector<uint64_t> &words, std::vector<double2> &pal);
+
+// The table form of a plan: segmented for A >= 3 (sharing the leading indices
+// pays: 22 % faster than packed on 4He, 31 % on 3He), factored for A = 4 with
+// integer coefficients, packed for A = 2, plain when neither fits;
+// WICK_TABLE_FORM=plain|packed|segmented|segmented-palette selects one
+// (testing; segmented uses integer-coefficient words when the coefficients
+// allow, segmented-palette never). words/pal receive the words and palette of
+// the word forms; seg the segmented form's chunk layout.
+int choose_table(const wick_plan_s *p, SegTable &seg, std::vector<uint64_t> &words, std::vector<double2> &pal)
+{
+    const char *form_env = std::getenv("WICK_TABLE_FORM");
+    const std::string form = form_env ? form_env : "";
+    const bool want_seg = form == "segmented" || form == "segmented-palette" || (form.empty() && p->A >= 3);
+    if (want_seg && (factor_table(p, seg) || segment_table(p, seg))) {
+        words.swap(seg.words);
+        pal = seg.pal;
+        return !seg.g.empty() ? kFormFactored : seg.unit ? kFormSegInt : kFormSegPalette;
+    }
+    if ((form.empty() || form == "packed") && pack_table(p, words, pal)) return kFormPacked;
+    return kFormPlain;
+}
+
+// Work of a table per time slice: words with two and with one leaf (zero
+// padding words not counted) and lanes with a segment; a plain or packed
+// table has one word per term.
+struct TableWork {
+    int32_t form = -1;
+    int64_t w2 = 0, w1 = 0, segs = 0;
+};
+TableWork table_work(int form, const SegTable &seg, const std::vector<uint64_t> &words, int64_t n_terms)
+{
+    TableWork w;
+    w.form = form;
+    if (form < kFormSegPalette) {
+        w.w1 = n_terms;
+        return w;
+    }
+    for (size_t c = 0; c < seg.base.size(); ++c) {
+        const int steps = seg.len[c] & 0xffff;
+        for (int l = 0; l < 64; ++l) {
+            bool any = false;
+            for (int j = 0; j < steps; ++j) {
+                const uint64_t v = words[seg.base[c] + (size_t)j * 64 + l];
+                if (!v) continue;
+                any = true;
+                const bool two = form == kFormSegPalette ? ((v >> 50) & 0xff) != 0 : (v >> 53) != 0;
+                ++(two ? w.w2 : w.w1);
+            }
+            w.segs += any;
+        }
+    }
+    return w;
+}
+std::map<const wick_plan_s *, TableWork> g_work;  // under g_dev_mu
+
+// The table work of a plan: recorded when its table was uploaded, else the
+// table is built on the host (no device needed) and the result kept.
+TableWork plan_work(const wick_plan_s *p)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        auto it = g_work.find(p);
+        if (it != g_work.end()) return it->second;
+    }
+    SegTable seg;
+    std::vector<uint64_t> words;
+    std::vector<double2> pal;
+    const int f = choose_table(p, seg, words, pal);
+    const TableWork w = table_work(f, seg, words, p->n_terms);
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    g_work.emplace(p, w);
+    return w;
+}
+
 
 wick_status check_groups(const wick_plan_s *p)
 {
@@ -617,28 +943,17 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
         }
     }
     const size_t nt = (size_t)p->n_terms;
-    // table form: segmented for A >= 3 (sharing the leading indices pays:
-    // 22 % faster than packed on 4He, 31 % on 3He), packed for A = 2, plain
-    // when neither fits; WICK_TABLE_FORM=plain|packed|segmented|segmented-palette
-    // selects one (testing; segmented uses integer-coefficient words when the
-    // coefficients allow, segmented-palette never)
-    const char *form_env = std::getenv("WICK_TABLE_FORM");
-    const std::string form = form_env ? form_env : "";
     std::vector<uint64_t> words;
     std::vector<double2> pal;
     SegTable seg;
-    const bool segmented = (form == "segmented" || form == "segmented-palette" || (form.empty() && p->A >= 3)) &&
-                           segment_table(p, seg);
-    const bool packed = !segmented && (form.empty() || form == "packed") && pack_table(p, words, pal);
-    if (segmented) {
-        words.swap(seg.words);
-        pal = seg.pal;
-    }
+    const int tform = choose_table(p, seg, words, pal);
+    const bool segmented = tform >= kFormSegPalette, packed = tform == kFormPacked;
+    if (!g_work.count(p)) g_work[p] = table_work(tform, seg, words, p->n_terms);
     const size_t coef_n = p->coef_real ? nt : 2 * nt;
     auto undo = [&] {
         for (void *q : {(void *)d.groups, (void *)d.desc, (void *)d.nuc, (void *)d.nuc_split, (void *)d.kidx,
                         (void *)d.coef, (void *)d.words, (void *)d.pal, (void *)d.seg_prefix, (void *)d.chunk_base,
-                        (void *)d.chunk_len})
+                        (void *)d.chunk_len, (void *)d.chunk_g})
             if (q) (void)hipFree(q);
     };
     const bool word_form = segmented || packed;
@@ -648,6 +963,7 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
         (segmented && (e = hipMalloc(&d.seg_prefix, seg.prefix.size() * sizeof(uint32_t))) != hipSuccess) ||
         (segmented && (e = hipMalloc(&d.chunk_base, seg.base.size() * sizeof(int64_t))) != hipSuccess) ||
         (segmented && (e = hipMalloc(&d.chunk_len, seg.len.size() * sizeof(int32_t))) != hipSuccess) ||
+        (!seg.g.empty() && (e = hipMalloc(&d.chunk_g, seg.g.size() * sizeof(int32_t))) != hipSuccess) ||
         (!word_form && (e = hipMalloc(&d.kidx, std::max<size_t>(1, nt * p->A) * sizeof(uint16_t))) != hipSuccess) ||
         (!word_form && (e = hipMalloc(&d.coef, std::max<size_t>(1, coef_n) * sizeof(double))) != hipSuccess)) {
         undo();
@@ -659,7 +975,9 @@ wick_status device_plan(wick_plan_s *p, hipStream_t s, DevPlan **out)
         d.coef_unit = seg.unit;
         if ((e = hipMemcpy(d.seg_prefix, seg.prefix.data(), seg.prefix.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemcpy(d.chunk_base, seg.base.data(), seg.base.size() * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(d.chunk_len, seg.len.data(), seg.len.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) {
+            (e = hipMemcpy(d.chunk_len, seg.len.data(), seg.len.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+            (!seg.g.empty() &&
+             (e = hipMemcpy(d.chunk_g, seg.g.data(), seg.g.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)) {
             undo();
             return hip_fail(e, "plan upload hipMemcpy");
         }
@@ -1502,6 +1820,7 @@ void release_device_tables(wick_plan_s *p)
 {
     release_plain_tables(p);
     std::lock_guard<std::mutex> lk(g_dev_mu);
+    g_work.erase(p);
     auto it = g_dev.find(p);
     if (it == g_dev.end()) return;
     int cur = 0;
@@ -1520,9 +1839,11 @@ void release_device_tables(wick_plan_s *p)
         (void)hipFree(d.seg_prefix);
         (void)hipFree(d.chunk_base);
         (void)hipFree(d.chunk_len);
+        (void)hipFree(d.chunk_g);
     }
     (void)hipSetDevice(cur);
     g_dev.erase(it);
+    g_work.erase(p);
 }
 
 }  // namespace wick
@@ -1599,6 +1920,18 @@ wick_status wick_plan_stats(wick_plan_t p, int64_t *n_enum, int64_t *n_groups, i
     if (n_groups) *n_groups = p->n_groups;
     if (n_terms) *n_terms = p->n_terms;
     if (bound) *bound = p->bound;
+    return WICK_OK;
+}
+
+wick_status wick_plan_sum_work(wick_plan_t p, int32_t *form, int64_t *words2, int64_t *words1, int64_t *segments)
+{
+    if (!p) return fail(WICK_EINVAL, "wick_plan_sum_work: null plan");
+    TableWork w;
+    WICK_TRY(w = wick::plan_work(p));
+    if (form) *form = w.form;
+    if (words2) *words2 = w.w2;
+    if (words1) *words1 = w.w1;
+    if (segments) *segments = w.segs;
     return WICK_OK;
 }
 

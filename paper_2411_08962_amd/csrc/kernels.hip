@@ -1038,6 +1038,9 @@ __device__ __forceinline__ void term_sum_seg(const double2 *__restrict__ sB, int
 // multiplies each segment's sum once. Chunk index, length and base are the
 // same for the whole wave and held in scalar registers, so the loop control
 // and the word addresses cost no vector instructions.
+// A = 4 tables are factored (chunk_g): the first ng = chunk_g[c] steps of a
+// chunk sum the lane's prefix group G, the later ones its list M, and the
+// lane adds unit * G * M; there is no prefix product.
 template <int A, int NTG>
 __device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, const TermTable &tab, int c0, int c1,
                                               double (&ar)[kMaxTG], double (&ai)[kMaxTG])
@@ -1047,14 +1050,24 @@ __device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, co
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     c0 = __builtin_amdgcn_readfirstlane(c0);
     c1 = __builtin_amdgcn_readfirstlane(c1);
+    constexpr bool kFactored = A == 4;
     const double unit = (double)tab.coef_unit;
     for (int c = c0 + wave; c < c1; c += kCThreads / 64) {
-        const uint32_t pre = tab.seg_prefix[(int64_t)c * 64 + lane];
-        double sx[NTG], sy[NTG];
+        double sx[NTG], sy[NTG], gx[NTG], gy[NTG];
 #pragma unroll
-        for (int tg = 0; tg < NTG; ++tg) sx[tg] = sy[tg] = 0.0;
+        for (int tg = 0; tg < NTG; ++tg) sx[tg] = sy[tg] = gx[tg] = gy[tg] = 0.0;
         const int cl = __builtin_amdgcn_readfirstlane(tab.chunk_len[c]);
         const int nodes = cl & 0xffff, two = cl >> 16;
+        const int ng = kFactored ? __builtin_amdgcn_readfirstlane(tab.chunk_g[c]) : 0;
+        // factored: the sum so far is the prefix group's; the list's starts
+        auto take_g = [&] {
+#pragma unroll
+            for (int tg = 0; tg < NTG; ++tg) {
+                gx[tg] = sx[tg];
+                gy[tg] = sy[tg];
+                sx[tg] = sy[tg] = 0.0;
+            }
+        };
         const uint64_t *wp = tab.words + tab.chunk_base[c] + lane;
         auto eval = [&](uint64_t w, auto leaf1) {
             constexpr bool kLeaf1 = decltype(leaf1)::value;
@@ -1105,15 +1118,19 @@ __device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, co
         if (nodes > 0) fetch(0, cur);
         for (int k0 = 0; k0 < nodes; k0 += kPrefetch) {
             if (k0 + kPrefetch < nodes) fetch(k0 + kPrefetch, nxt);
-            if (k0 + kPrefetch <= two) {
+            // (ng <= two: the prefix-group steps use the two-leaf form)
+            const bool switch_inside = kFactored && k0 < ng && ng < k0 + kPrefetch;
+            if (kFactored && k0 == ng) take_g();
+            if (k0 + kPrefetch <= two && !switch_inside) {
 #pragma unroll
                 for (int u = 0; u < kPrefetch; ++u) eval(cur[u], kBoth);
             } else if (k0 >= two && k0 + kPrefetch <= nodes) {
 #pragma unroll
                 for (int u = 0; u < kPrefetch; ++u) eval(cur[u], kLeaf0);
-            } else {  // the steps where leaf 1 ends, or the chunk's last steps
+            } else {  // the steps where G or leaf 1 ends, or the chunk's last steps
 #pragma unroll
                 for (int u = 0; u < kPrefetch; ++u) {
+                    if (kFactored && u > 0 && k0 + u == ng) take_g();
                     if (k0 + u < two) eval(cur[u], kBoth);
                     else if (k0 + u < nodes) eval(cur[u], kLeaf0);
                 }
@@ -1121,18 +1138,29 @@ __device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, co
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u) cur[u] = nxt[u];
         }
+        if constexpr (kFactored) {
+            if (ng >= nodes) take_g();  // no list steps (not built; kept for safety)
 #pragma unroll
-        for (int tg = 0; tg < NTG; ++tg) {
-            double px = unit, py = 0.0;
-#pragma unroll
-            for (int a = 0; a < A - 2; ++a) {
-                const double2 b = sB[(int)((pre >> (kPackBits * a)) & kMask) * NTG + tg];
-                const double x = px * b.x - py * b.y;
-                py = px * b.y + py * b.x;
-                px = x;
+            for (int tg = 0; tg < NTG; ++tg) {
+                const double px = unit * gx[tg], py = unit * gy[tg];
+                ar[tg] += px * sx[tg] - py * sy[tg];
+                ai[tg] += px * sy[tg] + py * sx[tg];
             }
-            ar[tg] += px * sx[tg] - py * sy[tg];
-            ai[tg] += px * sy[tg] + py * sx[tg];
+        } else {
+            const uint32_t pre = tab.seg_prefix[(int64_t)c * 64 + lane];
+#pragma unroll
+            for (int tg = 0; tg < NTG; ++tg) {
+                double px = unit, py = 0.0;
+#pragma unroll
+                for (int a = 0; a < A - 2; ++a) {
+                    const double2 b = sB[(int)((pre >> (kPackBits * a)) & kMask) * NTG + tg];
+                    const double x = px * b.x - py * b.y;
+                    py = px * b.y + py * b.x;
+                    px = x;
+                }
+                ar[tg] += px * sx[tg] - py * sy[tg];
+                ai[tg] += px * sy[tg] + py * sx[tg];
+            }
         }
     }
 }

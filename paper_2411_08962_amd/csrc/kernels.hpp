@@ -108,6 +108,16 @@ constexpr int kMaxPalette = 256;
 // of two-leaf nodes, and each lane holds its two-leaf nodes first, so a
 // chunk's steps j >= chunk_len[c] >> 16 have no leaf 1 in any lane and the
 // term sum skips that gather there.
+//
+// Factored form (A = 4 with integer words; chunk_g set). With the two index
+// positions of fewest distinct pairs taken as the prefix (i, j) and the two
+// others as node and leaf, the terms of each prefix form a list which,
+// divided by g (gcd of its q, sign of the first), many prefixes share:
+//   C = unit * sum_m G_m M_m,  G_m = sum over the prefixes of list m of g B[i] B[j].
+// A lane's segment is a piece of one list (at most 64 words, two-leaf words
+// first): its first chunk_g[c] steps hold G_m as words (node i, leaves j,
+// q = g; zero words pad a shorter group), the later ones the piece's list
+// words; the lane adds unit * G * (its piece's sum). seg_prefix is unused.
 constexpr int kNodeLeaves = 2;
 constexpr int kIntCoefMax = 1023;
 struct TermTable {
@@ -121,6 +131,7 @@ struct TermTable {
     const uint32_t *seg_prefix;  // [n_chunks * 64]: A-2 indices of 14 bits
     const int64_t *chunk_base;   // [n_chunks]
     const int32_t *chunk_len;    // [n_chunks]: nodes per lane, plus (steps with a leaf 1) << 16
+    const int32_t *chunk_g;      // [n_chunks]: factored form (A = 4), steps of prefix-group words
     int32_t n_chunks;
     int32_t coef_unit;           // segmented form: 0 palette words, else integer-coefficient words
 };

@@ -54,7 +54,7 @@ EXPORTS = ["wick_plan", "wick_plan_std", "wick_plan_info", "wick_plan_stats", "w
            "wick_point_info", "wick_point_correlator", "wick_point_destroy", "wick_gevp_plan", "wick_gevp_info",
            "wick_gevp_table", "wick_gevp_kinds", "wick_gevp_contract", "wick_gevp_destroy", "wick_gevp_plan_std",
            "wick_plan_std_pair", "wick_point_blocks_correlator", "wick_contract_noalloc",
-           "wick_autotune_batch"]
+           "wick_autotune_batch", "wick_plan_sum_work"]
 
 _lib = None
 
@@ -76,6 +76,8 @@ def lib():
     L.wick_plan_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                   ctypes.POINTER(ctypes.c_double)]
     L.wick_plan_table.argtypes = [P, P, P]
+    L.wick_plan_sum_work.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                     ctypes.POINTER(i64)]
     L.wick_plan_kind.argtypes = [P, i32, P, ctypes.POINTER(i32), P, P, P]
     L.wick_plan_save.argtypes = [P, ctypes.c_char_p]
     L.wick_plan_load.argtypes = [ctypes.c_char_p, pp]
@@ -109,7 +111,7 @@ def lib():
     L.wick_point_destroy.restype = None
     L.wick_last_error.restype = ctypes.c_char_p
     L.wick_version.restype = ctypes.c_char_p
-    for name in ("wick_plan", "wick_plan_std", "wick_plan_info", "wick_plan_stats", "wick_plan_table",
+    for name in ("wick_plan", "wick_plan_std", "wick_plan_info", "wick_plan_stats", "wick_plan_table", "wick_plan_sum_work",
                  "wick_plan_kind", "wick_plan_save", "wick_plan_load", "wick_plan_truncate", "wick_blocks",
                  "wick_contract",
                  "wick_correlator", "wick_autotune", "wick_shutdown", "wick_profile", "wick_profile_read",
@@ -162,6 +164,16 @@ class Plan:
         e, g, n, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
         _check(lib().wick_plan_stats(self._h, ctypes.byref(e), ctypes.byref(g), ctypes.byref(n), ctypes.byref(b)))
         return {"n_enumerated": e.value, "n_groups": g.value, "n_terms": n.value, "false_merge_bound": b.value}
+
+    SUM_FORMS = ("plain", "packed", "segmented-palette", "segmented", "factored")
+
+    def sum_work(self):
+        """Work of the term sum per time slice: {"form", "words2", "words1",
+        "segments"} (see wick_plan_sum_work)."""
+        f, w2, w1, sg = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().wick_plan_sum_work(self._h, ctypes.byref(f), ctypes.byref(w2), ctypes.byref(w1),
+                                        ctypes.byref(sg)))
+        return {"form": self.SUM_FORMS[f.value], "words2": w2.value, "words1": w1.value, "segments": sg.value}
 
     def table(self):
         """(kidx [A, N] uint16, coef [N] complex128)."""

@@ -70,6 +70,23 @@ def test_helium4_full_plan_matches_oracle():
     assert plan_kind_order(op, pl) != sink_kind_order(op)
     assert sorted(plan_kind_order(op, pl)) == list(range(len(op.kinds)))
     check_plan(op, pl, *small(V=2))
+    # its term sum takes the factored form: the 364752 prefixes of the best
+    # leading pair share 28751 lists, so the words are far fewer than the terms
+    w = pl.sum_work()
+    assert w["form"] == "factored"
+    assert 0 < w["words2"] + w["words1"] < pl.n_terms // 10 and w["segments"] > 0
+
+
+@pytest.mark.parametrize("name,form", [("2H", "packed"), ("3He", "segmented"), ("3H", "segmented")])
+def test_term_sum_work_accounts_for_every_term(name, form):
+    # every term sits in exactly one word slot of the unfactored forms (a
+    # two-leaf word holds two terms), and every segment is a lane with work
+    pl = W.plan_std(name)
+    w = pl.sum_work()
+    assert w["form"] == form
+    assert 2 * w["words2"] + w["words1"] == pl.n_terms
+    if form == "segmented":
+        assert 0 < w["segments"] <= w["words2"] + w["words1"]
 
 
 @pytest.mark.parametrize("a", [0, 1, 2, 3])
