@@ -418,16 +418,22 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
 //   C = unit * sum_m G_m M_m,  M_m = sum over the words of list m of
 //   B[node] (q0 B[leaf0] + q1 B[leaf1]),  G_m = sum over the prefixes of
 //   list m of g B[i] B[j],
-// where the G words pair the prefixes of one i as node i with leaves j. This
+// where each prefix is one G word (node i, leaf j, q = g; the prefixes of a
+// list have distinct i and distinct j in every built-in nucleus, so there is
+// nothing to pair, and the term sum gathers no leaf 1 for G words). This
 // evaluates each list once for all its prefixes (4He: 28751 lists for 364752
 // prefixes). Each list's words (two-leaf words first) are cut into pieces of
-// at most kPieceWords; a piece is one lane's segment and carries all the G
-// words of its list. Pieces are sorted by length, then by their two-leaf
-// words, and dealt to the 64 lanes of a chunk; chunk c holds g[c] steps of G
-// words (fewer in a lane padded with zero words), then its list words.
-constexpr int kPieceWords = 64;
+// at most piece_words (kPieceWords, or WICK_PIECE_WORDS for measurement); a
+// piece is one lane's segment and carries all the G words of its list.
+// Longer pieces repeat G less often but make fewer, longer chunks. Pieces are
+// sorted by length, then by their two-leaf words, and dealt to the 64 lanes of
+// a chunk; chunk c holds g[c] steps of G words (fewer in a lane padded with
+// zero words), then its list words.
+constexpr int kPieceWords = 256;
 bool factor_table(const wick_plan_s *p, SegTable &out)
 {
+    const char *piece_env = std::getenv("WICK_PIECE_WORDS");
+    const uint32_t piece_words = piece_env ? (uint32_t)std::max(8, std::min(4096, std::atoi(piece_env))) : kPieceWords;
     const size_t nt = (size_t)p->n_terms;
     if (p->A != 4 || (int)p->kinds.size() > kMaxLdsKinds || nt == 0 || nt > 0xffffffffULL) return false;
     const char *form_env = std::getenv("WICK_TABLE_FORM");
@@ -567,18 +573,9 @@ bool factor_table(const wick_plan_s *p, SegTable &out)
         }
         mw.insert(mw.end(), one.begin(), one.end());
         mw_off[m + 1] = mw.size();
-        const auto &mem = members[m];  // prefixes in lexicographic order
-        for (size_t a = 0; a < mem.size();) {
-            const Prefix &y = pre[mem[a]];
-            const uint32_t i = ix(0, ord[y.i0]);
-            if (a + 1 < mem.size() && ix(0, ord[pre[mem[a + 1]].i0]) == i) {
-                const Prefix &z = pre[mem[a + 1]];
-                gw.push_back(word(i, ix(1, ord[y.i0]), y.g, ix(1, ord[z.i0]), z.g));
-                a += 2;
-            } else {
-                gw.push_back(word(i, ix(1, ord[y.i0]), y.g, 0, 0));
-                a += 1;
-            }
+        for (uint32_t pi : members[m]) {  // one G word per prefix
+            const Prefix &y = pre[pi];
+            gw.push_back(word(ix(0, ord[y.i0]), ix(1, ord[y.i0]), y.g, 0, 0));
         }
         gw_off[m + 1] = gw.size();
     }
@@ -589,8 +586,8 @@ bool factor_table(const wick_plan_s *p, SegTable &out)
     std::vector<Piece> pieces;
     for (size_t m = 0; m < n_lists; ++m) {
         const uint32_t n = (uint32_t)(mw_off[m + 1] - mw_off[m]);
-        for (uint32_t a = 0; a < n; a += kPieceWords) {
-            const uint32_t len = std::min<uint32_t>(kPieceWords, n - a);
+        for (uint32_t a = 0; a < n; a += piece_words) {
+            const uint32_t len = std::min<uint32_t>(piece_words, n - a);
             const uint32_t two = a < mw_two[m] ? std::min<uint32_t>(len, mw_two[m] - a) : 0;
             pieces.push_back({(uint32_t)m, (uint32_t)mw_off[m] + a, len, two});
         }
@@ -615,7 +612,7 @@ bool factor_table(const wick_plan_s *p, SegTable &out)
             M = std::max(M, lane_len[si]);
             two = std::max(two, lane_two[si]);
         }
-        if (G + M > 0xffff) return false;
+        if (G + M > 0xffff) return false;  // (a chunk's steps fit 16 bits)
         out.base[c] = (int64_t)total;
         out.g[c] = G;
         out.len[c] = (G + M) | ((G + two) << 16);

@@ -1039,8 +1039,8 @@ __device__ __forceinline__ void term_sum_seg(const double2 *__restrict__ sB, int
 // same for the whole wave and held in scalar registers, so the loop control
 // and the word addresses cost no vector instructions.
 // A = 4 tables are factored (chunk_g): the first ng = chunk_g[c] steps of a
-// chunk sum the lane's prefix group G, the later ones its list M, and the
-// lane adds unit * G * M; there is no prefix product.
+// chunk sum the lane's prefix group G (one-leaf words), the later ones its
+// list M, and the lane adds unit * G * M; there is no prefix product.
 template <int A, int NTG>
 __device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, const TermTable &tab, int c0, int c1,
                                               double (&ar)[kMaxTG], double (&ai)[kMaxTG])
@@ -1118,21 +1118,24 @@ __device__ __forceinline__ void term_sum_segi(const double2 *__restrict__ sB, co
         if (nodes > 0) fetch(0, cur);
         for (int k0 = 0; k0 < nodes; k0 += kPrefetch) {
             if (k0 + kPrefetch < nodes) fetch(k0 + kPrefetch, nxt);
-            // (ng <= two: the prefix-group steps use the two-leaf form)
-            const bool switch_inside = kFactored && k0 < ng && ng < k0 + kPrefetch;
+            // steps [0, ng): prefix-group words (factored; one leaf), [ng, two):
+            // list words with two leaves in some lane, [two, nodes): one leaf
             if (kFactored && k0 == ng) take_g();
-            if (k0 + kPrefetch <= two && !switch_inside) {
-#pragma unroll
-                for (int u = 0; u < kPrefetch; ++u) eval(cur[u], kBoth);
-            } else if (k0 >= two && k0 + kPrefetch <= nodes) {
+            const int hi = k0 + kPrefetch;
+            if (hi <= ng || (k0 >= two && hi <= nodes)) {
 #pragma unroll
                 for (int u = 0; u < kPrefetch; ++u) eval(cur[u], kLeaf0);
+            } else if (k0 >= ng && hi <= two) {
+#pragma unroll
+                for (int u = 0; u < kPrefetch; ++u) eval(cur[u], kBoth);
             } else {  // the steps where G or leaf 1 ends, or the chunk's last steps
 #pragma unroll
                 for (int u = 0; u < kPrefetch; ++u) {
-                    if (kFactored && u > 0 && k0 + u == ng) take_g();
-                    if (k0 + u < two) eval(cur[u], kBoth);
-                    else if (k0 + u < nodes) eval(cur[u], kLeaf0);
+                    const int j = k0 + u;
+                    if (kFactored && u > 0 && j == ng) take_g();
+                    if (j < ng) eval(cur[u], kLeaf0);
+                    else if (j < two) eval(cur[u], kBoth);
+                    else if (j < nodes) eval(cur[u], kLeaf0);
                 }
             }
 #pragma unroll

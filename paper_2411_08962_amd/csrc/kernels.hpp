@@ -114,10 +114,10 @@ constexpr int kMaxPalette = 256;
 // others as node and leaf, the terms of each prefix form a list which,
 // divided by g (gcd of its q, sign of the first), many prefixes share:
 //   C = unit * sum_m G_m M_m,  G_m = sum over the prefixes of list m of g B[i] B[j].
-// A lane's segment is a piece of one list (at most 64 words, two-leaf words
-// first): its first chunk_g[c] steps hold G_m as words (node i, leaves j,
-// q = g; zero words pad a shorter group), the later ones the piece's list
-// words; the lane adds unit * G * (its piece's sum). seg_prefix is unused.
+// A lane's segment is a piece of one list (two-leaf words first): its first
+// chunk_g[c] steps hold G_m as one-leaf words (node i, leaf j, q = g; zero
+// words pad a shorter group), the later ones the piece's list words; the
+// lane adds unit * G * (its piece's sum). seg_prefix is unused.
 constexpr int kNodeLeaves = 2;
 constexpr int kIntCoefMax = 1023;
 struct TermTable {
