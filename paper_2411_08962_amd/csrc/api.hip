@@ -127,7 +127,7 @@ struct DevPlan {
     int32_t *chunk_len = nullptr;
     int32_t *chunk_g = nullptr;  // factored table only
     int n_chunks = 0, seg_len = 0;
-    int coef_unit = 0;  // segmented table: integer-coefficient words when nonzero
+    double coef_unit = 0.0;  // segmented table: integer-coefficient words when nonzero
 };
 
 TermTable table_of(const DevPlan *d, const wick_plan_s *p)
@@ -183,27 +183,50 @@ struct SegTable {
     std::vector<int32_t> g;    // factored form: steps of prefix-group words per chunk (else empty)
     std::vector<double2> pal;
     int seg_len = 0;
-    int32_t unit = 0;  // integer-coefficient words (see TermTable) when nonzero
+    double unit = 0.0;  // integer-coefficient words (see TermTable) when nonzero
 };
 
-// The common unit of a real table whose coefficients are integers: the gcd
-// g of their magnitudes when every coefficient is q * g with |q| <= the
-// word's limit, else 0 (the palette form is used).
-int32_t integer_unit(const wick_plan_s *p)
+// The common unit of a real table: a number u with every coefficient equal
+// to q * u for an integer q, |q| <= the word's limit, to within 2^-50 of the
+// coefficient (so the words carry the coefficients to FP64 accuracy), else 0
+// (the palette form is used). u is the smallest |coefficient| divided by the
+// smallest d <= 64 that makes every ratio an integer, times the gcd of the
+// resulting q: the gcd of integer coefficients (4He: 48), or for instance
+// 1/24 for an operator whose coefficients are multiples of 1/24.
+double coef_unit_of(const wick_plan_s *p)
 {
     const size_t nt = (size_t)p->n_terms;
-    uint64_t g = 0;
+    double s0 = INFINITY;
     for (size_t n = 0; n < nt; ++n) {
         const double re = p->coef_re[n];
-        if (p->coef_im[n] != 0.0 || re != std::floor(re) || std::fabs(re) >= 2147483648.0 || re == 0.0) return 0;
-        uint64_t a = (uint64_t)std::fabs(re), b = g;
-        while (b) { const uint64_t r = a % b; a = b; b = r; }
-        g = a;
+        if (p->coef_im[n] != 0.0 || re == 0.0 || !std::isfinite(re)) return 0.0;
+        s0 = std::min(s0, std::fabs(re));
     }
-    if (g == 0 || g > ((uint64_t)1 << 20)) return 0;
-    for (size_t n = 0; n < nt; ++n)
-        if (std::fabs(p->coef_re[n]) / (double)g > kIntCoefMax) return 0;
-    return (int32_t)g;
+    if (!(s0 < INFINITY)) return 0.0;
+    auto exact = [](double c, double q, double u) { return std::fabs(c - q * u) <= 0x1p-50 * std::fabs(c); };
+    for (int d = 1; d <= 64; ++d) {
+        const double u = s0 / d;
+        uint64_t g = 0;
+        bool ok = true;
+        for (size_t n = 0; n < nt && ok; ++n) {
+            const double q = std::nearbyint(p->coef_re[n] / u);
+            if (std::fabs(q) > 64.0 * kIntCoefMax || !exact(p->coef_re[n], q, u)) {
+                ok = false;
+                break;
+            }
+            uint64_t a = (uint64_t)std::fabs(q), b = g;
+            while (b) { const uint64_t r = a % b; a = b; b = r; }
+            g = a;
+        }
+        if (!ok) continue;
+        const double unit = u * (double)g;
+        for (size_t n = 0; n < nt; ++n) {
+            const double q = std::nearbyint(p->coef_re[n] / unit);
+            if (std::fabs(q) > kIntCoefMax || !exact(p->coef_re[n], q, unit)) return 0.0;
+        }
+        return unit;
+    }
+    return 0.0;
 }
 
 // LDS bank balance of the gathers of integer-coefficient words. Step j of a
@@ -287,9 +310,9 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
     // integer words for A <= 3 (an A = 4 table with integer coefficients
     // takes the factored form, which sets chunk_g)
     const char *form_env = std::getenv("WICK_TABLE_FORM");
-    out.unit = (form_env && std::string(form_env) == "segmented-palette") || A == 4 ? 0 : integer_unit(p);
+    out.unit = (form_env && std::string(form_env) == "segmented-palette") || A == 4 ? 0.0 : coef_unit_of(p);
     auto qbits = [&](uint32_t t) {  // 11-bit two's complement of coef / unit
-        const int64_t q = (int64_t)(p->coef_re[t] / out.unit);
+        const int64_t q = std::llround(p->coef_re[t] / out.unit);
         return (uint64_t)q & 0x7ff;
     };
     const uint16_t *k = p->kidx.data();
@@ -438,8 +461,8 @@ bool factor_table(const wick_plan_s *p, SegTable &out)
     if (p->A != 4 || (int)p->kinds.size() > kMaxLdsKinds || nt == 0 || nt > 0xffffffffULL) return false;
     const char *form_env = std::getenv("WICK_TABLE_FORM");
     if (form_env && std::string(form_env) == "segmented-palette") return false;
-    out.unit = integer_unit(p);
-    if (!out.unit) return false;
+    out.unit = coef_unit_of(p);
+    if (out.unit == 0.0) return false;
     out.pal.assign(1, double2{0.0, 0.0});  // not read by integer words
     const uint16_t *k = p->kidx.data();
     // the leading pair of positions: fewest distinct index pairs (a bitmap of
@@ -471,7 +494,7 @@ bool factor_table(const wick_plan_s *p, SegTable &out)
             if (a != perm[0] && a != perm[1]) perm[o++] = a;
     }
     auto ix = [&](int a, uint32_t t) { return (uint32_t)k[(size_t)perm[a] * nt + t]; };
-    auto qv = [&](uint32_t t) { return (int32_t)(p->coef_re[t] / out.unit); };
+    auto qv = [&](uint32_t t) { return (int32_t)std::llround(p->coef_re[t] / out.unit); };
     // terms in lexicographic order of their reordered index tuples
     std::vector<uint32_t> ord(nt), tmp(nt);
     for (size_t t = 0; t < nt; ++t) ord[t] = (uint32_t)t;
@@ -684,7 +707,7 @@ int choose_table(const wick_plan_s *p, SegTable &seg, std::vector<uint64_t> &wor
     if (want_seg && (factor_table(p, seg) || segment_table(p, seg))) {
         words.swap(seg.words);
         pal = seg.pal;
-        return !seg.g.empty() ? kFormFactored : seg.unit ? kFormSegInt : kFormSegPalette;
+        return !seg.g.empty() ? kFormFactored : seg.unit != 0.0 ? kFormSegInt : kFormSegPalette;
     }
     if ((form.empty() || form == "packed") && pack_table(p, words, pal)) return kFormPacked;
     return kFormPlain;

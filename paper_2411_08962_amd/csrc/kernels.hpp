@@ -98,12 +98,14 @@ constexpr int kMaxPalette = 256;
 // leaf 0 [28,36), leaf 1 [36,50), palette index of leaf 1 [50,58); palette
 // entry 0 is zero.
 //
-// Integer-coefficient words (coef_unit != 0: every coefficient is a real
-// integer multiple q * coef_unit with |q| <= 1023, true of every built-in
-// nucleus): leaf 0 [0,14), node index [14,28), leaf 1 [28,42), q of leaf 0
-// [42,53) and q of leaf 1 [53,64), both two's complement. The coefficient
-// is formed in registers (q * coef_unit is an exact integer), so no palette
-// is read from LDS. q = 0 marks a missing leaf (index 0, weight zero) and a
+// Integer-coefficient words (coef_unit != 0: every coefficient is q *
+// coef_unit for an integer q, |q| <= 1023, to within 2^-50 of it; true of
+// every built-in nucleus, with coef_unit an integer, and of operators whose
+// coefficients are multiples of one rational scale): leaf 0 [0,14), node
+// index [14,28), leaf 1 [28,42), q of leaf 0 [42,53) and q of leaf 1
+// [53,64), both two's complement. The lane sums with the integers q (exact
+// in FP64) and multiplies by coef_unit once per segment, so no palette is
+// read from LDS. q = 0 marks a missing leaf (index 0, weight zero) and a
 // zero word is padding. Segments of equal length are sorted by their number
 // of two-leaf nodes, and each lane holds its two-leaf nodes first, so a
 // chunk's steps j >= chunk_len[c] >> 16 have no leaf 1 in any lane and the
@@ -133,7 +135,7 @@ struct TermTable {
     const int32_t *chunk_len;    // [n_chunks]: nodes per lane, plus (steps with a leaf 1) << 16
     const int32_t *chunk_g;      // [n_chunks]: factored form (A = 4), steps of prefix-group words
     int32_t n_chunks;
-    int32_t coef_unit;           // segmented form: 0 palette words, else integer-coefficient words
+    double coef_unit;            // segmented form: 0 palette words, else integer-coefficient words
 };
 
 // The term sum stages the blocks of up to kMaxTG consecutive time slices of

@@ -73,3 +73,31 @@ def test_random_batches_of_builtin_nuclei(seed):
         C = w.correlator(plans, items, du, dd, use_graph=use_graph).cpu().numpy()
         for row, (pi, cfg) in enumerate(items):
             check(makers[pi](), plans[pi], C, hu, hd, cfg, row)
+
+
+@pytest.mark.parametrize("seed", [1, 3, 4, 6])
+@pytest.mark.parametrize("piece", ["8", "13", "256"])
+def test_random_helium4_factored_term_sum(monkeypatch, seed, piece):
+    # sparsified 4He operators (A = 4, coefficients multiples of one rational
+    # unit: the factored table form; 97k to 227k terms) with list pieces of 8,
+    # 13 or 256 words, so that lists split into many pieces and the switch from
+    # prefix-group to list words falls at many offsets of the 8-word blocks the
+    # kernel prefetches; against the oracle through wick_contract, and with
+    # the palette and packed forms of the same operator (the batched entry
+    # point takes kinds of nucleon form only: the full 4He batch covers the
+    # factored form there)
+    rng = np.random.default_rng(5000 + seed)
+    op = ops.sparsify(ops.helium4(), int(rng.integers(3, 6)), rng, keep_patterns=int(rng.integers(1, 4)))
+    dims = (2, 2, 1, 2)
+    w = W()
+    monkeypatch.setenv("WICK_PIECE_WORDS", piece)
+    hu, hd, du, dd = props(6000 + seed, 1, dims, np.complex128)
+    for form in ("segmented", "segmented-palette", "packed"):
+        monkeypatch.setenv("WICK_TABLE_FORM", form)
+        pl = w.plan(**to_wick(op))  # a fresh plan: its table is built under this form
+        assert pl.n_terms > 0
+        work = pl.sum_work()
+        assert work["form"] == {"segmented": "factored", "segmented-palette": "segmented-palette",
+                                "packed": "packed"}[form]
+        C = w.contract(pl, w.blocks(pl, du, dd)).cpu().numpy()
+        check(op, pl, C, hu, hd, 0, 0)

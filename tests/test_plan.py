@@ -77,6 +77,22 @@ def test_helium4_full_plan_matches_oracle():
     assert 0 < w["words2"] + w["words1"] < pl.n_terms // 10 and w["segments"] > 0
 
 
+def test_rational_unit_tables_take_the_integer_word_forms():
+    # with the operator scaled by 1/24 the table's coefficients are multiples
+    # of 1/24, not integers: the A = 4 table still takes the factored form and
+    # the A = 3 one the segmented integer form, with the same word counts as
+    # the unscaled operator's
+    for base, form in ((ops.helium4, "factored"), (ops.helium3, "segmented")):
+        op = ops.sparsify(base(), 4, np.random.default_rng(5001), keep_patterns=2)
+        args = to_wick(op)
+        pl1 = W.plan(**args)
+        pl24 = W.plan(**dict(args, scale=args["scale"] / 24))
+        _, coef = pl24.table()
+        assert pl24.n_terms > 0 and not np.all(coef.real == np.round(coef.real))
+        assert pl24.sum_work()["form"] == form
+        assert pl24.sum_work() == pl1.sum_work()
+
+
 @pytest.mark.parametrize("name,form", [("2H", "packed"), ("3He", "segmented"), ("3H", "segmented")])
 def test_term_sum_work_accounts_for_every_term(name, form):
     # every term sits in exactly one word slot of the unfactored forms (a
