@@ -238,7 +238,8 @@ double coef_unit_of(const wick_plan_s *p)
 // quarter-wave; 6.3 when in addition every quarter-wave uses the same
 // lane-to-group pattern). A sum does not depend on the order of its words,
 // so each lane's words are reordered greedily: at each step the lanes of a
-// half-wave in turn take, among their next kBalanceWindow words, the one
+// half-wave in turn take, among their next kBalanceWindow words (or
+// WICK_BALANCE_WINDOW, for measurement), the one
 // whose three groups are least used so far in that half-wave at that step
 // (balancing per quarter-wave instead measured 2 % slower on the
 // 64-configuration batch). A lane's words fall into parts that are reordered
@@ -256,6 +257,8 @@ void balance_banks(SegTable &out, const std::vector<int32_t> &lane_len, const st
     // slice 0 at 16-byte slot e * ntg (slice t adds t to every lane alike)
     auto grp = [ntg](uint64_t e) { return (int)((e * (uint64_t)ntg) & 15); };
     const size_t n_chunks = out.base.size();
+    const char *win_env = std::getenv("WICK_BALANCE_WINDOW");  // for measurement
+    const int window = win_env ? std::max(1, std::min(256, std::atoi(win_env))) : kBalanceWindow;
     auto work = [&](size_t c_lo, size_t c_hi) {
         for (size_t c = c_lo; c < c_hi; ++c) {
             uint64_t *w = out.words.data() + out.base[c];
@@ -275,7 +278,7 @@ void balance_banks(SegTable &out, const std::vector<int32_t> &lane_len, const st
                             if (jm >= ll[l]) continue;
                             part_end = G + (jm < l2[l] ? l2[l] : ll[l]);
                         }
-                        const int end = std::min(part_end, j + kBalanceWindow);
+                        const int end = std::min(part_end, j + window);
                         int best = j, best_cost = 1 << 30;
                         for (int k = j; k < end; ++k) {
                             const uint64_t v = w[(size_t)k * 64 + l];
