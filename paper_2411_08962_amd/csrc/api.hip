@@ -349,8 +349,15 @@ bool segment_table(const wick_plan_s *p, SegTable &out)
         nodes.push_back({(uint32_t)i, (uint8_t)(j - i)});
         i = j;
     }
-    // segments: runs of nodes sharing the first A-2 indices, at most seg_nodes nodes
-    const int seg_nodes = (int)std::min<size_t>(64, std::max<size_t>(8, nodes.size() / 65536));
+    // segments: runs of nodes sharing the first A-2 indices, at most seg_nodes
+    // nodes: nodes / 8192 within [8, 128], so that a table has about 8192
+    // segments (3He: 113; segments of 14, 32, 64 and 128 measured 5.41, 5.11,
+    // 5.02 and 4.98 ms for the 64-configuration batch's term sum: each segment
+    // and chunk costs a prefix product and a pipeline start); WICK_SEG_WORDS
+    // overrides, for measurement
+    const char *seg_env = std::getenv("WICK_SEG_WORDS");
+    const int seg_nodes = seg_env ? std::max(1, std::min(4096, std::atoi(seg_env)))
+                                  : (int)std::min<size_t>(128, std::max<size_t>(8, nodes.size() / 8192));
     out.seg_len = seg_nodes * kNodeLeaves;
     struct Seg {
         uint32_t first, n, two;  // first node, number of nodes, of them with two leaves
