@@ -264,6 +264,34 @@ def test_split_precision_late_time_slices(prec):
     check_C(ops.deuteron(), pl, C, hu, hd, [40, 63], tol=SPLIT_TOL[prec])
 
 
+@pytest.mark.parametrize("prec", ["p32", "pb6"])
+@pytest.mark.parametrize("pattern", ["zero-first-batch", "alternating"])
+def test_split_precision_batches_of_very_different_magnitude(prec, pattern):
+    # the split modes scale their FP32 (or BF16-limb) operands by a power of
+    # two taken per 16-site batch; 64 sites = four batches whose magnitudes
+    # differ: "zero-first-batch": the first batch is exactly zero and the
+    # others ~2^-45 (three-entry products ~2^-135, below the FP32 normal
+    # range unless scaled); "alternating": batches at 2^-40 and 2^+40 (the
+    # scale must move by 80 binades between batches, folding the FP32 sums)
+    torch = _torch()
+    w = W()
+    pl = w.plan_std("2H")
+    dims = (4, 4, 4, 2)  # 64 sites, sites x-fastest: batch b = sites 16b .. 16b+15
+    hu0, hd0, _, _ = props(13, 1, dims)
+    site = np.arange(64).reshape(4, 4, 4)  # [z, y, x] -> flat site index
+    batch = site // 16
+    if pattern == "zero-first-batch":
+        f = np.where(batch == 0, 0.0, 2.0 ** -45)
+    else:
+        f = np.where(batch % 2 == 0, 2.0 ** -40, 2.0 ** 40)
+    f = f[None, None, :, :, :, None, None]
+    hu, hd = hu0 * f, hd0 * f
+    du, dd = torch.from_numpy(hu).cuda(), torch.from_numpy(hd).cuda()
+    C = w.contract(pl, w.blocks(pl, du, dd, prec)).cpu().numpy()
+    assert np.all(np.isfinite(C))
+    check_C(ops.deuteron(), pl, C, hu, hd, range(dims[3]), tol=SPLIT_TOL[prec])
+
+
 # ------------------------------------------------------------------ autotune
 @pytest.mark.parametrize("name,dims,prec", [("2H", (4, 4, 4, 8), "p64"), ("3He", (3, 3, 2, 3), "pb6")])
 def test_autotune_cache_and_parity(tmp_path, name, dims, prec):
