@@ -77,6 +77,23 @@ def test_helium4_full_plan_matches_oracle():
     assert 0 < w["words2"] + w["words1"] < pl.n_terms // 10 and w["segments"] > 0
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_random_segmented_tables_hold_every_term_once(seed):
+    # sparsified A = 3 operators (irregular node and segment structure, a
+    # rational unit): the segmented integer-word table holds every term in
+    # exactly one word slot, and every segment has at least one word
+    rng = np.random.default_rng(7000 + seed)
+    base = [ops.helium3, lambda: ops.triton(1)][seed % 2]()
+    op = ops.sparsify(base, int(rng.integers(3, 7)), rng, keep_patterns=int(rng.integers(1, 5)))
+    pl = W.plan(**to_wick(op))
+    if pl.n_terms == 0:
+        pytest.skip("the sparsified operator has no terms")
+    w = pl.sum_work()
+    assert w["form"] == "segmented"
+    assert 2 * w["words2"] + w["words1"] == pl.n_terms
+    assert 0 < w["segments"] <= w["words2"] + w["words1"]
+
+
 def test_rational_unit_tables_take_the_integer_word_forms():
     # with the operator scaled by 1/24 the table's coefficients are multiples
     # of 1/24, not integers: the A = 4 table still takes the factored form and
