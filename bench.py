@@ -661,7 +661,7 @@ def point_bench(args):
         "paper_s_per_time_slice_24cubed": PAPER_POINT_24.get(nucleus),
         "kernel_ms": ms,
     }
-    if nucleus in ("2H", "3He"):
+    if nucleus in ("2H", "3He", "4He"):
         # the same correlator in the block form (per-site blocks and the plane-wave table)
         pl = W.plan_std(nucleus)
         Cb = torch.empty_like(C)

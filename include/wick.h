@@ -350,7 +350,8 @@ void wick_point_destroy(wick_point_t plan);
  * B_x[kidx_{a,n}], scale included). The per-site blocks are built in chunks
  * of site-slices and summed with the wick_contract kernels (the site-slices
  * take the place of time slices). On the 24^3 lattice it is the faster route
- * for deuteron and helium-3, the determinant route for helium-4. Same
+ * for deuteron, helium-3 and helium-4 (whose table takes the factored form
+ * there as everywhere). Same
  * arguments and errors as wick_point_correlator, with a plan from wick_plan /
  * wick_plan_std; it allocates a second per-stream workspace for the site
  * blocks (at most 512 MB) and the per-site sums. */

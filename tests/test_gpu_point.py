@@ -177,9 +177,11 @@ def test_point_block_form_matches_oracle(name, make, dims):
 
 
 def test_point_block_form_equals_determinants_on_a_lattice():
-    # the two routes to the same point-sink correlator, on 4^3 x 3 (2H) and 3x3x2 x 2 (3He)
+    # the two routes to the same point-sink correlator, on 4^3 x 3 (2H), 3x3x2 x 2 (3He)
+    # and 2x2x2 x 2 (4He: the block form's term sum takes the factored table)
     w = W()
-    for name, op, dims in (("2H", ops.deuteron(), (4, 4, 4, 3)), ("3He", ops.helium3(), (3, 3, 2, 2))):
+    for name, op, dims in (("2H", ops.deuteron(), (4, 4, 4, 3)), ("3He", ops.helium3(), (3, 3, 2, 2)),
+                           ("4He", ops.helium4(), (2, 2, 2, 2))):
         hu, hd, du, dd = props(972, 1, dims)
         Cb = w.point_blocks_correlator(w.plan_std(name), du, dd).cpu().numpy()[0]
         Cd = w.point_correlator(w.point_plan_std(name), du, dd).cpu().numpy()[0]
@@ -205,11 +207,12 @@ def test_point_block_form_general_plan_complex64_and_empty():
 
 
 def test_point_routes_agree_full_size():
-    """Determinants and the block form on the benchmark lattice (24^3, two time
-    slices): two independent algorithms for the same point-sink correlator."""
+    """Determinants and the block form on the benchmark lattice (24^3; two time
+    slices, one for 4He): two independent algorithms for the same point-sink
+    correlator."""
     w = W()
-    for name in ("2H", "3He"):
-        hu, hd, du, dd = props(974, 1, (24, 24, 24, 2))
+    for name in ("2H", "3He", "4He"):
+        hu, hd, du, dd = props(974, 1, (24, 24, 24, 1 if name == "4He" else 2))
         Cd = w.point_correlator(w.point_plan_std(name), du, dd).cpu().numpy()[0]
         Cb = w.point_blocks_correlator(w.plan_std(name), du, dd).cpu().numpy()[0]
         a, b = Cd[:, 0] + 1j * Cd[:, 1], Cb[:, 0] + 1j * Cb[:, 1]
