@@ -50,3 +50,27 @@ def test_contract_noalloc_needs_a_resident_plan():
     assert e.value.status == w.EINVAL and "not on this device" in str(e.value)
     torch.cuda.synchronize()
     assert not torch.any(out != 0)
+
+
+def test_contract_noalloc_factored_table():
+    # an A = 4 table in the factored form (a sparsified 4He operator, 97 200
+    # terms): the allocation-free call equals wick_contract bitwise, then again
+    # on a smaller set of blocks
+    import torch
+    import paper_2411_08962_amd as w
+    from oracle import operators as ops
+    from tests.helpers import to_wick
+    print("wick_contract_noalloc: sparsified 4He (factored table) 2x2x1x3, then 1x1x1x1", flush=True)
+    rng = np.random.default_rng(5004)
+    op = ops.sparsify(ops.helium4(), int(rng.integers(3, 6)), rng, keep_patterns=int(rng.integers(1, 4)))
+    pl = w.plan(**to_wick(op))
+    assert pl.sum_work()["form"] == "factored"
+    for wid, dims in ((35, (2, 2, 1, 3)), (36, (1, 1, 1, 1))):
+        B = _blocks(w, pl, wid, 1, dims)
+        ref = w.contract(pl, B)
+        out = torch.full((1, dims[3], 2), float("nan"), dtype=torch.float64, device="cuda")
+        w.contract_noalloc(pl, B, out)
+        torch.cuda.synchronize()
+        got, want = out.cpu().numpy(), ref.cpu().numpy()
+        assert np.all(np.isfinite(got)), dims
+        assert np.array_equal(got, want), (dims, np.max(np.abs(got - want)))
