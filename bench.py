@@ -262,6 +262,14 @@ def main():
               "achieved": tf_c, "peak": 78.6, "peak_name": "FP64 vector ALU", "unit": "TFLOP/s",
               "frac": tf_c / 78.6, "traffic": tr.get("contract"), "flops_per_launch": sum_flops,
               "avg_launch_ms": avg_c}
+        # the flat count, 6A + 2 flops per deduplicated term and time slice: what a
+        # per-term evaluation would execute; above the peak when the table's words
+        # share sub-sums (the factored form), so a rate of the method, not of the ALU
+        flat = sum(plans[n].n_terms * T * (6 * plans[n].A + 2) for n, _ in items)
+        if nc:
+            rc["flat_6A2_flops_per_launch"] = flat
+            rc["flat_6A2_tflops"] = flat / (avg_c * 1e-3) / 1e12
+            rc["flat_6A2_over_fp64_alu_peak"] = rc["flat_6A2_tflops"] / 78.6
         return rb, rc
 
     main_run = runs[prec]
